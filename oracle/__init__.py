@@ -1,0 +1,129 @@
+"""ORACLE — TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 CPU reference for the Vecchia log-likelihood and its gradient
+(Eq. (7) evaluated as in Algorithm 1 of Pan et al.; the gradient is the
+derivative of each conditional term).  Only ``tests/``, the smoke check and
+the benchmark's CPU-baseline leg may import this package.  It shares no code
+with the GPU library.  The arithmetic lives in ``vecchia_oracle.c``; this
+file only builds it and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vecchia_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle library in place with gcc."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", *CFLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"])
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_terms.restype = ctypes.c_int64
+        lib.oracle_terms.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P,
+                                     ctypes.c_int64, P, P, ctypes.c_int32]
+        lib.oracle_loglik.restype = ctypes.c_int64
+        lib.oracle_loglik.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, P, P, P,
+                                      ctypes.c_int32]
+        lib.oracle_matern.restype = None
+        lib.oracle_matern.argtypes = [P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
+        lib.oracle_sum.restype = ctypes.c_double
+        lib.oracle_sum.argtypes = [P, ctypes.c_int64]
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    """Bad arguments (code < 0) or a failed conditional (code = i + 1 of the first failure)."""
+
+    def __init__(self, code: int):
+        self.code = int(code)
+        what = "invalid argument" if code == -1 else "out of memory" if code == -2 else \
+            f"non-positive pivot or conditional variance at point {code - 1}"
+        super().__init__(f"oracle: {what}")
+
+
+def _prep(locs, z, nbr, m):
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = locs.shape[0]
+    if locs.shape != (n, 2) or z.shape != (n,):
+        raise ValueError("locs must be [n][2] and z [n]")
+    if m > 0:
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        if nbr.shape != (n, m):
+            raise ValueError("nbr must be [n][m]")
+    else:
+        nbr = np.zeros((max(n, 1), 1), dtype=np.int32)
+    return locs, z, nbr, n
+
+
+def terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_grad: bool = False, threads: int = 0,
+          raise_on_fail: bool = True):
+    """Per-conditional l_i (and dl_i/d(sigma2, beta, tau2)) for the points idx (default all)."""
+    locs, z, nbr, n = _prep(locs, z, nbr, m)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    if idx is None:
+        nidx = n
+        idx_p = None
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        nidx = idx.shape[0]
+        idx_p = idx.ctypes.data
+    ell = np.empty(max(nidx, 1), dtype=np.float64)
+    g = np.empty((max(nidx, 1), 3), dtype=np.float64) if with_grad else None
+    rc = _load().oracle_terms(locs.ctypes.data, z.ctypes.data, nbr.ctypes.data, n, m, float(nu), th.ctypes.data,
+                              idx_p, nidx, ell.ctypes.data, g.ctypes.data if g is not None else None, threads)
+    if rc < 0 or (rc > 0 and raise_on_fail):
+        raise OracleError(rc)
+    ell = ell[:nidx]
+    return (ell, g[:nidx]) if with_grad else ell
+
+
+def loglik(locs, z, nbr, m: int, nu: float, theta, with_grad: bool = False, threads: int = 0):
+    """Sum of l_i (Neumaier, ascending i); with_grad also returns the gradient (sigma2, beta, tau2)."""
+    locs, z, nbr, n = _prep(locs, z, nbr, m)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    out = np.zeros(1)
+    g = np.zeros(3) if with_grad else None
+    rc = _load().oracle_loglik(locs.ctypes.data, z.ctypes.data, nbr.ctypes.data, n, m, float(nu), th.ctypes.data,
+                               out.ctypes.data, g.ctypes.data if g is not None else None, threads)
+    if rc != 0:
+        raise OracleError(rc)
+    return (float(out[0]), g) if with_grad else float(out[0])
+
+
+def matern(d, nu: float, sigma2: float, beta: float, with_dbeta: bool = False):
+    """The oracle's covariance values (and d/dbeta) at distances d."""
+    d = np.ascontiguousarray(d, dtype=np.float64).ravel()
+    out = np.empty_like(d)
+    db = np.empty_like(d) if with_dbeta else None
+    _load().oracle_matern(d.ctypes.data, d.size, float(nu), float(sigma2), float(beta), out.ctypes.data,
+                          db.ctypes.data if db is not None else None)
+    return (out, db) if with_dbeta else out
+
+
+def compensated_sum(x) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    return float(_load().oracle_sum(x.ctypes.data, x.size))

@@ -1,0 +1,334 @@
+/*
+ * ORACLE — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct FP64 CPU evaluation of the Vecchia
+ * approximated Gaussian-process log-likelihood and of its gradient with
+ * respect to (sigma^2, beta, tau^2).  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this file's library.  It shares no
+ * code with the GPU library: it has its own covariance, Cholesky, solves and
+ * summation.
+ *
+ * What it computes (Pan et al., "GPU-Accelerated Vecchia Approximations of
+ * Gaussian Processes for Geospatial Data using Batched Matrix Computations"):
+ *
+ *   Eq. (7): log p(y) ~= sum_i log p(y_i | y_{J_i}), where J_i holds the
+ *   min(i, m) nearest previously-ordered points of point i (0-based).  Each
+ *   conditional is Gaussian with
+ *       mean      mu_i = v^T Sigma_NN^{-1} y_N
+ *       variance  c_i  = Sigma_ii - v^T Sigma_NN^{-1} v,
+ *   formed as in Algorithm 1: covariance generation (sigma, Sigma, v), a
+ *   Cholesky factor of Sigma_NN (POTRF), two triangular solves (TRSV) for
+ *   v' = L^{-1} v and y' = L^{-1} y_N, the two dot products mu = v'.y' and
+ *   v'.v', and the univariate Gaussian term, all summed.
+ *
+ *   Readings taken where the paper is silent or garbled:
+ *   - The univariate term uses c_i as a VARIANCE (the algorithm subtracts a
+ *     variance from a variance, so its "sigma" is a variance):
+ *       l_i = -1/2 (log 2 pi + log c_i + (y_i - mu_i)^2 / c_i).
+ *   - The first block is not a joint density over the first m points but the
+ *     chain of short conditioning sets (k = i < m); by Eqs. (4)-(5) the two
+ *     are equal.
+ *   - Covariance, Eq. (2), with the distance scaled by beta alone (Table II's
+ *     beta values give correlation 1/45 at the effective range under this
+ *     scaling).  For nu = 1/2, 3/2, 5/2 the Bessel form reduces exactly to
+ *       nu=0.5: s2 e^{-r};  nu=1.5: s2 (1+r) e^{-r};
+ *       nu=2.5: s2 (1 + r + r^2/3) e^{-r},  r = ||s_a - s_b|| / beta.
+ *   - A nugget tau^2 is added to the diagonal of Sigma_NN and to Sigma_ii
+ *     (entries with equal indices), never to the cross vector v.
+ *   - The gradient (not in the paper) is the derivative of each l_i:
+ *       dl_i/dp = 1/2 (r^2 - 1/c) dc_p + r dmu_p,  r = (y_i - mu_i)/c_i,
+ *       dc_p  = dSigma_ii/dp - 2 a^T dv/dp + a^T dSigma_NN/dp a,
+ *       dmu_p = (dv/dp)^T s - a^T dSigma_NN/dp s,
+ *     with a = Sigma_NN^{-1} v and s = Sigma_NN^{-1} y_N, each obtained by a
+ *     back substitution with L^T.  dC/dsigma2 = C/sigma2 (nugget excluded),
+ *     dSigma/dtau2 = I on Sigma_NN and 1 on Sigma_ii, dC/dbeta = -r/beta dC/dr.
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp.  Per-conditional
+ * results are stored per i and summed afterwards in ascending i with
+ * Neumaier compensation, so totals do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORACLE_LOG_2PI 1.8378770664093454835606594728112
+
+/* Error codes returned (negative) by the entry points. */
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* Matern covariance, Eq. (2), closed form for half-integer smoothness. */
+static double matern(double d, double nu, double sigma2, double beta) {
+    double r = d / beta;
+    double e = exp(-r);
+    if (nu == 0.5) return sigma2 * e;
+    if (nu == 1.5) return sigma2 * (1.0 + r) * e;
+    /* nu == 2.5 */
+    return sigma2 * (1.0 + r + r * r / 3.0) * e;
+}
+
+/* d/dbeta of the covariance above: dC/dbeta = (dC/dr)(dr/dbeta), dr/dbeta = -r/beta. */
+static double matern_dbeta(double d, double nu, double sigma2, double beta) {
+    double r = d / beta;
+    double e = exp(-r);
+    double dcdr;
+    if (nu == 0.5) dcdr = -sigma2 * e;
+    else if (nu == 1.5) dcdr = sigma2 * (e - (1.0 + r) * e);
+    else dcdr = sigma2 * ((1.0 + 2.0 * r / 3.0) * e - (1.0 + r + r * r / 3.0) * e);
+    return dcdr * (-r / beta);
+}
+
+static double dist(const double *a, const double *b) {
+    double dx = a[0] - b[0];
+    double dy = a[1] - b[1];
+    return sqrt(dx * dx + dy * dy);
+}
+
+typedef struct {
+    double *S, *L, *v, *yN, *vp, *yp, *a, *s, *Sp, *vpd;
+} work_t;
+
+static int work_alloc(work_t *w, int m) {
+    size_t mm = (size_t)(m > 0 ? m : 1);
+    w->S = (double *)malloc(mm * mm * sizeof(double));
+    w->L = (double *)malloc(mm * mm * sizeof(double));
+    w->Sp = (double *)malloc(mm * mm * sizeof(double));
+    w->v = (double *)malloc(mm * sizeof(double));
+    w->yN = (double *)malloc(mm * sizeof(double));
+    w->vp = (double *)malloc(mm * sizeof(double));
+    w->yp = (double *)malloc(mm * sizeof(double));
+    w->a = (double *)malloc(mm * sizeof(double));
+    w->s = (double *)malloc(mm * sizeof(double));
+    w->vpd = (double *)malloc(mm * sizeof(double));
+    return w->S && w->L && w->Sp && w->v && w->yN && w->vp && w->yp && w->a && w->s && w->vpd;
+}
+
+static void work_free(work_t *w) {
+    free(w->S); free(w->L); free(w->Sp); free(w->v); free(w->yN);
+    free(w->vp); free(w->yp); free(w->a); free(w->s); free(w->vpd);
+}
+
+/*
+ * One conditional: l_i and (optionally) its gradient g[3] = dl_i/d(sigma2, beta, tau2).
+ * Returns 0, or 1 when a pivot of the Cholesky factor or c_i is not positive
+ * (or not finite).
+ */
+static int conditional(const double *locs, const double *z, const int32_t *nbr_row, int64_t i, int k,
+                       double nu, double sigma2, double beta, double tau2, work_t *w, double *ell,
+                       double *g) {
+    const double *si = locs + 2 * i;
+    /* covariance generation (Algorithm 1, batched kernel step) */
+    for (int a = 0; a < k; ++a) {
+        const double *sa = locs + 2 * (int64_t)nbr_row[a];
+        for (int b = 0; b < k; ++b) {
+            const double *sb = locs + 2 * (int64_t)nbr_row[b];
+            w->S[a * k + b] = matern(dist(sa, sb), nu, sigma2, beta) + (a == b ? tau2 : 0.0);
+        }
+        w->v[a] = matern(dist(sa, si), nu, sigma2, beta);
+        w->yN[a] = z[nbr_row[a]];
+    }
+    double Sii = sigma2 + tau2;
+
+    /* Cholesky-Banachiewicz, row by row (POTRF) */
+    for (int r = 0; r < k; ++r) {
+        for (int c = 0; c <= r; ++c) {
+            double acc = w->S[r * k + c];
+            for (int q = 0; q < c; ++q) acc -= w->L[r * k + q] * w->L[c * k + q];
+            if (r == c) {
+                if (!(acc > 0.0) || !isfinite(acc)) return 1;
+                w->L[r * k + r] = sqrt(acc);
+            } else {
+                w->L[r * k + c] = acc / w->L[c * k + c];
+            }
+        }
+    }
+    /* forward substitutions (TRSV): v' = L^{-1} v, y' = L^{-1} y_N */
+    for (int r = 0; r < k; ++r) {
+        double av = w->v[r], ay = w->yN[r];
+        for (int q = 0; q < r; ++q) {
+            av -= w->L[r * k + q] * w->vp[q];
+            ay -= w->L[r * k + q] * w->yp[q];
+        }
+        w->vp[r] = av / w->L[r * k + r];
+        w->yp[r] = ay / w->L[r * k + r];
+    }
+    /* dot products: mu = v'.y', c = Sigma_ii - v'.v' */
+    double mu = 0.0, vv = 0.0;
+    for (int r = 0; r < k; ++r) {
+        mu += w->vp[r] * w->yp[r];
+        vv += w->vp[r] * w->vp[r];
+    }
+    double c = Sii - vv;
+    if (!(c > 0.0) || !isfinite(c)) return 1;
+    double res = z[i] - mu;
+    *ell = -0.5 * (ORACLE_LOG_2PI + log(c) + res * res / c);
+    if (!g) return 0;
+
+    /* back substitutions with L^T: a = Sigma_NN^{-1} v, s = Sigma_NN^{-1} y_N */
+    for (int r = k - 1; r >= 0; --r) {
+        double aa = w->vp[r], ss = w->yp[r];
+        for (int q = r + 1; q < k; ++q) {
+            aa -= w->L[q * k + r] * w->a[q];
+            ss -= w->L[q * k + r] * w->s[q];
+        }
+        w->a[r] = aa / w->L[r * k + r];
+        w->s[r] = ss / w->L[r * k + r];
+    }
+    double rr = res / c;
+    double half = 0.5 * (rr * rr - 1.0 / c);
+    for (int p = 0; p < 3; ++p) {
+        double Siip;
+        /* derivative blocks: Sp = dSigma_NN/dp, vpd = dv/dp, Siip = dSigma_ii/dp */
+        for (int a = 0; a < k; ++a) {
+            const double *sa = locs + 2 * (int64_t)nbr_row[a];
+            for (int b = 0; b < k; ++b) {
+                const double *sb = locs + 2 * (int64_t)nbr_row[b];
+                double d = dist(sa, sb);
+                double val;
+                if (p == 0) val = matern(d, nu, sigma2, beta) / sigma2;
+                else if (p == 1) val = matern_dbeta(d, nu, sigma2, beta);
+                else val = (a == b) ? 1.0 : 0.0;
+                w->Sp[a * k + b] = val;
+            }
+            double di = dist(sa, si);
+            if (p == 0) w->vpd[a] = matern(di, nu, sigma2, beta) / sigma2;
+            else if (p == 1) w->vpd[a] = matern_dbeta(di, nu, sigma2, beta);
+            else w->vpd[a] = 0.0;
+        }
+        Siip = (p == 1) ? 0.0 : 1.0;
+        double aSa = 0.0, aSs = 0.0, av = 0.0, vs = 0.0;
+        for (int a = 0; a < k; ++a) {
+            double rowa = 0.0, rows = 0.0;
+            for (int b = 0; b < k; ++b) {
+                rowa += w->Sp[a * k + b] * w->a[b];
+                rows += w->Sp[a * k + b] * w->s[b];
+            }
+            aSa += w->a[a] * rowa;
+            aSs += w->a[a] * rows;
+            av += w->a[a] * w->vpd[a];
+            vs += w->vpd[a] * w->s[a];
+        }
+        double dc = Siip - 2.0 * av + aSa;
+        double dmu = vs - aSs;
+        g[p] = half * dc + rr * dmu;
+    }
+    return 0;
+}
+
+/* Neumaier-compensated sum of x[0..n) in ascending order. */
+static double neumaier(const double *x, int64_t n, int64_t stride) {
+    double s = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = x[i * stride];
+        double t = s + v;
+        if (fabs(s) >= fabs(v)) comp += (s - t) + v;
+        else comp += (v - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+static int valid_nu(double nu) { return nu == 0.5 || nu == 1.5 || nu == 2.5; }
+
+/*
+ * Per-conditional terms for the points listed in idx[0..nidx) (all points 0..n-1
+ * when idx is NULL, then nidx must equal n).
+ *   locs [n][2], z [n], nbr [n][m] int32 (row i: min(i,m) indices in [0,i), then -1)
+ *   theta = {sigma2, beta, tau2}
+ *   ell [nidx] receives l_i; grad [nidx][3] (may be NULL) receives dl_i/d(sigma2,beta,tau2).
+ * Returns 0; a negative error code for bad arguments; or (i+1) for the smallest
+ * listed point i whose conditional failed (its outputs are NaN).
+ */
+int64_t oracle_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                     const double *theta, const int64_t *idx, int64_t nidx, double *ell, double *grad,
+                     int32_t nthreads) {
+    if (!locs || !z || !theta || !ell || n < 0 || m < 0 || (m > 0 && !nbr) || nidx < 0) return ORACLE_EINVAL;
+    if (!idx && nidx != n) return ORACLE_EINVAL;
+    if (!valid_nu(nu) || !(theta[0] > 0) || !(theta[1] > 0) || !(theta[2] >= 0)) return ORACLE_EINVAL;
+    for (int64_t t = 0; t < nidx; ++t) {
+        int64_t i = idx ? idx[t] : t;
+        if (i < 0 || i >= n) return ORACLE_EINVAL;
+        int64_t k = i < m ? i : m;
+        for (int64_t q = 0; q < k; ++q) {
+            int32_t j = nbr[i * (int64_t)m + q];
+            if (j < 0 || j >= i) return ORACLE_EINVAL;
+        }
+    }
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int64_t first_fail = INT64_MAX;
+    int nomem = 0;
+#pragma omp parallel
+    {
+        work_t w;
+        int ok = work_alloc(&w, m);
+        if (!ok) {
+#pragma omp atomic write
+            nomem = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nidx; ++t) {
+            if (!ok) continue;
+            int64_t i = idx ? idx[t] : t;
+            int k = (int)(i < m ? i : m);
+            double g[3] = {0, 0, 0};
+            double e = 0.0;
+            int bad = conditional(locs, z, nbr + i * (int64_t)m, i, k, nu, theta[0], theta[1], theta[2], &w, &e,
+                                  grad ? g : NULL);
+            if (bad) {
+                e = NAN;
+                g[0] = g[1] = g[2] = NAN;
+#pragma omp critical
+                {
+                    if (i < first_fail) first_fail = i;
+                }
+            }
+            ell[t] = e;
+            if (grad) {
+                grad[3 * t + 0] = g[0];
+                grad[3 * t + 1] = g[1];
+                grad[3 * t + 2] = g[2];
+            }
+        }
+        work_free(&w);
+    }
+    if (nomem) return ORACLE_ENOMEM;
+    return first_fail == INT64_MAX ? 0 : first_fail + 1;
+}
+
+/*
+ * Whole log-likelihood: out[0] = sum_i l_i; grad[0..3) = sum_i dl_i/dp when grad != NULL.
+ * Sums are Neumaier-compensated in ascending i.  Return value as oracle_terms.
+ */
+int64_t oracle_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                      const double *theta, double *out, double *grad, int32_t nthreads) {
+    if (!out || n < 0) return ORACLE_EINVAL;
+    double *ell = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *g = grad ? (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double)) : NULL;
+    if (!ell || (grad && !g)) {
+        free(ell); free(g);
+        return ORACLE_ENOMEM;
+    }
+    int64_t rc = oracle_terms(locs, z, nbr, n, m, nu, theta, NULL, n, ell, g, nthreads);
+    if (rc >= 0) {
+        out[0] = neumaier(ell, n, 1);
+        if (grad)
+            for (int p = 0; p < 3; ++p) grad[p] = neumaier(g + p, n, 3);
+    }
+    free(ell);
+    free(g);
+    return rc;
+}
+
+/* The covariance entries this oracle uses, exported so tests can pin them against Eq. (2). */
+void oracle_matern(const double *d, int64_t n, double nu, double sigma2, double beta, double *out,
+                   double *dbeta) {
+    for (int64_t t = 0; t < n; ++t) {
+        out[t] = matern(d[t], nu, sigma2, beta);
+        if (dbeta) dbeta[t] = matern_dbeta(d[t], nu, sigma2, beta);
+    }
+}
+
+/* Neumaier sum exported for tests. */
+double oracle_sum(const double *x, int64_t n) { return neumaier(x, n, 1); }
