@@ -1,0 +1,168 @@
+"""Benchmark: Vecchia conditionals per second, FP64 log-likelihood + gradient.
+
+Default workload: n = 1,000,000 uniform points in the unit square, random
+order, m = 120 nearest previous neighbours, Matern nu = 0.5,
+theta = (sigma2, beta, tau2) = (1.5, 0.03, 1e-4), z ~ N(0, 1) i.i.d.
+One step = one full evaluation of the log-likelihood and its gradient
+(every conditional: gather, covariance, Cholesky, solves, adjoint, sums).
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  Extra objects:
+  roofline      algorithmic FP64 flops of the conditional kernel per launch
+                divided by its measured launch duration, against the FP64 peak;
+  cpu_baseline  the oracle timed on a bounded sample of the same workload on
+                the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Vecchia conditionals/sec (logL+grad, FP64) n=1M m=120; batched vs plain"
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 GHz x 128 flop/clk
+
+
+def la_flops_per_conditional(k: np.ndarray, with_grad: bool) -> np.ndarray:
+    """Algorithmic dense-LA flops of one conditional with k neighbours (the paper's flop model, Sec. IV-C):
+    POTRF k^3/3 + k^2/2 + k/6, two TRSVs 2k^2, the two dot products 4k; the gradient adds two
+    back substitutions, 2k^2.  Covariance generation (k(k+1)/2 kernel evaluations) is counted apart."""
+    k = k.astype(np.float64)
+    f = k ** 3 / 3 + k ** 2 / 2 + k / 6 + 2 * k ** 2 + 4 * k
+    if with_grad:
+        f = f + 2 * k ** 2
+    return f
+
+
+def workload_counts(n: int, m: int, with_grad: bool):
+    k = np.minimum(np.arange(n), m)
+    flops = float(la_flops_per_conditional(k, with_grad).sum())
+    evals = float((k * (k + 1) / 2 + k).sum()) * (2 if with_grad else 1)
+    gather_bytes = float((28 * k + 24).sum())
+    return flops, evals, gather_bytes
+
+
+def cpu_baseline(field, with_grad: bool, target_s: float = 15.0):
+    """The oracle on a bounded random sample of the workload's conditionals (same inputs)."""
+    import oracle
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    rng = np.random.default_rng(12345)
+    th = field.thetas[0]
+    size = 64
+    elapsed = 0.0
+    while True:
+        idx = np.sort(rng.choice(field.n, size, replace=False)).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.terms(field.locs, field.z, field.nbr, field.m, field.nu, th, idx=idx, with_grad=with_grad,
+                     threads=threads)
+        elapsed = time.perf_counter() - t0
+        if elapsed >= target_s * 0.5 or size >= field.n:
+            break
+        size = int(min(field.n, max(size * 2, size * target_s / max(elapsed, 1e-3) * 0.7)))
+    return {"value": size / elapsed, "unit": "conditionals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{size} conditionals drawn uniformly from the {field.n}-point workload "
+                      f"({'value+gradient' if with_grad else 'value'}), {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--m", type=int, default=120)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method's conditionals are independent and a multi-GPU run "
+              "would shard them by cost and all-reduce four doubles; this build measures one GPU's share.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_07412_amd as v
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    v.library()
+    t0 = time.time()
+    w = wl.config_large(n=args.n, m=args.m, knn_threads=min(os.cpu_count() or 1, 16))
+    f = w.fields[0]
+    print(f"# workload {w.name}: inputs ready in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    locs = torch.from_numpy(f.locs).to(dev)
+    z = torch.from_numpy(f.z).to(dev)
+    nbr = torch.from_numpy(f.nbr).to(dev)
+    theta = torch.from_numpy(f.thetas[0].copy()).to(dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(3, dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev)
+
+    def step():
+        v.vecchia_loglik_grad(locs, z, nbr, f.m, f.nu, theta, out=out, grad=grad, status=status, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = int(status.item())
+    if st != 0:
+        raise RuntimeError(f"status {st}")
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = float(np.mean(launch_ms))
+    print(f"# {args.steps} steps: wall {wall * 1e3 / args.steps:.3f} ms/step, events mean {ms:.3f} ms "
+          f"(min {min(launch_ms):.3f}); loglik {out.item():.12e} grad {grad.cpu().numpy()}",
+          file=sys.stderr, flush=True)
+
+    flops, evals, gbytes = workload_counts(f.n, f.m, True)
+    achieved = flops / (ms * 1e-3) / 1e12
+    value = f.n * args.steps / wall
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "conditionals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name} value+gradient", "n": f.n, "m": f.m, "nu": f.nu,
+                   "theta": [float(x) for x in f.thetas[0]], "form": "plain"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flops_per_launch": flops, "kernel_evals_per_launch": evals,
+                     "gather_bytes_per_launch": gbytes, "launch_ms": ms},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(f, True)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,124 @@
+/*
+ * vecchia.h — C ABI of the MI355X (gfx950) library that evaluates the Vecchia
+ * approximated Gaussian-process log-likelihood and its gradient in FP64.
+ *
+ * The method (Pan et al., "GPU-Accelerated Vecchia Approximations of Gaussian
+ * Processes for Geospatial Data using Batched Matrix Computations"):
+ *
+ *   Eq. (7)       log p(y) ~= sum_{i=0}^{n-1} log p(y_i | y_{J_i})
+ *   Algorithm 1   per point: covariance generation (sigma_i, Sigma_i, v_i),
+ *                 Cholesky of Sigma_i, triangular solves for v_i and y_{J_i},
+ *                 dot products giving the conditional mean and variance,
+ *                 univariate Gaussian term, sum over points.
+ *   Eq. (2)       Matern covariance with r = ||s_a - s_b|| / beta, here for
+ *                 smoothness nu in {0.5, 1.5, 2.5} in closed form:
+ *                 sigma2 e^-r, sigma2 (1+r) e^-r, sigma2 (1+r+r^2/3) e^-r.
+ *
+ * Additions that the paper does not have:
+ *   - a nugget tau2 on the diagonal of Sigma_NN and on Sigma_ii (not on v);
+ *   - the gradient dl/d(sigma2, beta, tau2) at fixed nu;
+ *   - batched evaluation of many parameter vectors and many fields.
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers marked [dev] are DEVICE pointers owned by the caller.  The
+ *     library never frees them and keeps no reference after the call.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     is asynchronous.  Entry points never synchronise the device, except the
+ *     batched planner, which documents it.
+ *   - locs  [dev] double [n][2]  row-major coordinates, already in the ordering.
+ *   - z     [dev] double [n]     observations (zero mean).
+ *   - nbr   [dev] int32  [n][m]  row i lists its min(i, m) conditioning points,
+ *                                each in [0, i), in any order; other slots are
+ *                                ignored (by convention -1).  Row 0 is empty.
+ *   - theta [dev] double [3]     (sigma2 > 0, beta > 0, tau2 >= 0), all finite.
+ *   - nu is 0.5, 1.5 or 2.5;  0 <= m <= VECCHIA_MAX_M.
+ *   - status [dev] int64 per evaluation, written by the device:
+ *         0                      success;
+ *         VECCHIA_STATUS_THETA   theta invalid (outputs NaN);
+ *         i + 1 (> 0)            point i is the smallest failing point: its
+ *                                block is not numerically positive definite
+ *                                (a pivot or the conditional variance is not
+ *                                positive and finite), an input is not finite,
+ *                                or a neighbour index is outside [0, i).
+ *                                The outputs of that evaluation are NaN.
+ *     The device checks every neighbour index before using it, so bad input
+ *     never causes an out-of-bounds access.
+ *   - Return value (synchronous): VECCHIA_OK or an error code below, for
+ *     argument or launch problems detected on the host.
+ *   - Results are deterministic: the same inputs give bitwise equal outputs,
+ *     whatever the launch order of the work.
+ */
+#ifndef VECCHIA_H
+#define VECCHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VECCHIA_MAX_M 160
+#define VECCHIA_STATUS_THETA (-1)
+
+enum vecchia_error {
+    VECCHIA_OK = 0,
+    VECCHIA_EINVAL = 1,        /* null pointer, n < 0, m < 0, bad nu, bad sizes */
+    VECCHIA_EUNSUPPORTED = 2,  /* m > VECCHIA_MAX_M, too many fields, unknown option */
+    VECCHIA_EHIP = 3,          /* a HIP runtime call or kernel launch failed */
+    VECCHIA_EWORKSPACE = 4     /* workspace missing or smaller than required */
+};
+
+/* Human-readable text for a return code. */
+const char *vecchia_strerror(int code);
+
+/* Library version string. */
+const char *vecchia_version(void);
+
+/*
+ * Workspace (bytes) that vecchia_loglik / vecchia_loglik_grad need for n points
+ * and m neighbours.  The caller allocates it on the device (256-byte aligned)
+ * and may reuse it across calls on the same stream.
+ */
+size_t vecchia_workspace_size(int64_t n, int32_t m);
+
+/*
+ * Log-likelihood, Eq. (7): out[0] = sum_i l_i with
+ *   l_i = -1/2 (log 2 pi + log c_i + (z_i - mu_i)^2 / c_i),
+ * mu_i and c_i the conditional mean and variance of point i given its set.
+ *   out      [dev] double[1]
+ *   status   [dev] int64[1]
+ *   ws       [dev] workspace of at least vecchia_workspace_size(n, m) bytes
+ * n = 0 gives out = 0.  Returns VECCHIA_OK or an error code.
+ */
+int vecchia_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                   const double *theta, double *out, int64_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Log-likelihood and its gradient with respect to (sigma2, beta, tau2) at fixed
+ * nu (the derivative of every l_i, summed; not in the paper).
+ *   out   [dev] double[1];  grad [dev] double[3] = (dl/dsigma2, dl/dbeta, dl/dtau2)
+ * Factors are recomputed inside the kernel; nothing of size n*m^2 is stored.
+ */
+int vecchia_loglik_grad(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                        const double *theta, double *out, double *grad, int64_t *status, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/*
+ * Per-point terms, for checking individual conditionals.
+ *   idx    [dev] int64[nidx] points to evaluate, each in [0, n); NULL = all
+ *          points (then nidx must equal n)
+ *   terms  [dev] double[nidx]      l_i for idx[t]
+ *   gterms [dev] double[nidx][3]   dl_i/d(sigma2, beta, tau2), or NULL
+ *   status [dev] int64[1]          as above, over the listed points
+ * An index outside [0, n) in idx marks status with t + 1 and yields NaN.
+ */
+int vecchia_loglik_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                         double nu, const double *theta, const int64_t *idx, int64_t nidx, double *terms,
+                         double *gterms, int64_t *status, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VECCHIA_H */

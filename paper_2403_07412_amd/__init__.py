@@ -1,0 +1,223 @@
+"""MI355X-native Vecchia Gaussian-process log-likelihood (FP64) — Python binding.
+
+The compute lives in ``libvecchia.so`` (hand-written HIP for gfx950, C ABI
+declared in ``include/vecchia.h``).  This module only marshals torch tensors
+(device memory and the current HIP stream) into that ABI; it has no numerical
+fallback.  Importing works without a GPU; calling needs the built library and
+a GPU, and fails loudly otherwise.
+
+Functions carry the C names:
+
+    vecchia_workspace_size(n, m)
+    vecchia_loglik(locs, z, nbr, m, nu, theta, ...)          -> (out[1], status[1])
+    vecchia_loglik_grad(locs, z, nbr, m, nu, theta, ...)     -> (out[1], grad[3], status[1])
+    vecchia_loglik_terms(locs, z, nbr, m, nu, theta, idx...) -> (terms, gterms, status)
+
+and ``loglik(locs, z, nbr, theta, nu, m)`` is the differentiable form
+(a ``torch.autograd.Function``): its backward returns grad_out * dl/dtheta,
+computed by the fused adjoint kernel in the forward pass.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvecchia.so")
+
+VECCHIA_MAX_M = 160
+VECCHIA_STATUS_THETA = -1
+_ERRORS = {1: "VECCHIA_EINVAL", 2: "VECCHIA_EUNSUPPORTED", 3: "VECCHIA_EHIP", 4: "VECCHIA_EWORKSPACE"}
+
+_lib = None
+
+
+class VecchiaError(RuntimeError):
+    """A synchronous error code returned by the C ABI."""
+
+    def __init__(self, code: int, what: str = ""):
+        self.code = int(code)
+        msg = _load().vecchia_strerror(self.code).decode() if _lib is not None else _ERRORS.get(code, "")
+        super().__init__(f"{what}: {_ERRORS.get(self.code, self.code)} ({msg})")
+
+
+class VecchiaNumericalError(RuntimeError):
+    """Device status: a conditional failed (status = i+1) or theta was invalid (status = -1)."""
+
+    def __init__(self, status: int):
+        self.status = int(status)
+        if status == VECCHIA_STATUS_THETA:
+            msg = "invalid covariance parameters"
+        else:
+            msg = f"point {status - 1}: block not positive definite, non-finite input or bad neighbour index"
+        super().__init__(msg)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_07412_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, D, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        lib.vecchia_strerror.restype = ctypes.c_char_p
+        lib.vecchia_strerror.argtypes = [ctypes.c_int]
+        lib.vecchia_version.restype = ctypes.c_char_p
+        lib.vecchia_version.argtypes = []
+        lib.vecchia_workspace_size.restype = SZ
+        lib.vecchia_workspace_size.argtypes = [I64, I32]
+        lib.vecchia_loglik.restype = ctypes.c_int
+        lib.vecchia_loglik.argtypes = [P, P, P, I64, I32, D, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_grad.restype = ctypes.c_int
+        lib.vecchia_loglik_grad.argtypes = [P, P, P, I64, I32, D, P, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_terms.restype = ctypes.c_int
+        lib.vecchia_loglik_terms.argtypes = [P, P, P, I64, I32, D, P, P, I64, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _load()
+
+
+def version() -> str:
+    return _load().vecchia_version().decode()
+
+
+# ------------------------------------------------------------------ marshalling
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("inputs must be contiguous device tensors")
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_inputs(locs, z, nbr, m):
+    if locs.dtype != torch.float64 or z.dtype != torch.float64:
+        raise TypeError("locs and z must be float64")
+    n = z.shape[0]
+    if tuple(locs.shape) != (n, 2):
+        raise ValueError("locs must be [n][2]")
+    if m > 0:
+        if nbr is None or nbr.dtype != torch.int32 or tuple(nbr.shape) != (n, m):
+            raise ValueError("nbr must be int32 [n][m]")
+    _dev_check(locs, z, nbr if m > 0 else None)
+    return n
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise VecchiaError(rc, what)
+
+
+def vecchia_workspace_size(n: int, m: int) -> int:
+    return int(_load().vecchia_workspace_size(int(n), int(m)))
+
+
+def _workspace(n, m, device, ws):
+    need = vecchia_workspace_size(n, m)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws
+
+
+def vecchia_loglik(locs, z, nbr, m: int, nu: float, theta, out=None, status=None, ws=None, stream=None):
+    """l = sum_i log p(z_i | z_{J_i}) on the device; returns (out[1], status[1]) without synchronising."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
+    _dev_check(theta, out, status)
+    ws = _workspace(n, m, dev, ws)
+    rc = _load().vecchia_loglik(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu), _ptr(theta),
+                                _ptr(out), _ptr(status), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_loglik")
+    return out, status
+
+
+def vecchia_loglik_grad(locs, z, nbr, m: int, nu: float, theta, out=None, grad=None, status=None, ws=None,
+                        stream=None):
+    """l and dl/d(sigma2, beta, tau2) on the device; returns (out[1], grad[3], status[1])."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    grad = torch.empty(3, dtype=torch.float64, device=dev) if grad is None else grad
+    status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
+    _dev_check(theta, out, grad, status)
+    ws = _workspace(n, m, dev, ws)
+    rc = _load().vecchia_loglik_grad(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
+                                     _ptr(theta), _ptr(out), _ptr(grad), _ptr(status), _ptr(ws), ws.numel(),
+                                     _stream(stream))
+    _check(rc, "vecchia_loglik_grad")
+    return out, grad, status
+
+
+def vecchia_loglik_terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_grad: bool = False, stream=None):
+    """Per-point l_i (and dl_i/dtheta) for the points idx (default all); returns (terms, gterms|None, status)."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    if idx is not None:
+        if idx.dtype != torch.int64:
+            raise TypeError("idx must be int64")
+        _dev_check(idx)
+        nidx = idx.shape[0]
+    else:
+        nidx = n
+    terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
+    gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
+    status = torch.empty(1, dtype=torch.int64, device=dev)
+    _dev_check(theta)
+    rc = _load().vecchia_loglik_terms(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
+                                      _ptr(theta), _ptr(idx), nidx, _ptr(terms), _ptr(gterms), _ptr(status),
+                                      _stream(stream))
+    _check(rc, "vecchia_loglik_terms")
+    return terms[:nidx], (gterms[:nidx] if gterms is not None else None), status
+
+
+def raise_on_status(status) -> None:
+    """Synchronises and raises VecchiaNumericalError when a device status word is non-zero."""
+    s = int(status.reshape(-1)[0].item())
+    if s != 0:
+        raise VecchiaNumericalError(s)
+
+
+# ------------------------------------------------------------------ autograd
+class VecchiaLogLik(torch.autograd.Function):
+    """l(theta) with the analytic adjoint; theta = (sigma2, beta, tau2) as a float64 device tensor [3]."""
+
+    @staticmethod
+    def forward(ctx, theta, locs, z, nbr, nu, m, check):
+        theta_c = theta.detach().contiguous()
+        if ctx.needs_input_grad[0]:
+            out, grad, status = vecchia_loglik_grad(locs, z, nbr, m, nu, theta_c)
+            ctx.save_for_backward(grad)
+        else:
+            out, status = vecchia_loglik(locs, z, nbr, m, nu, theta_c)
+        if check:
+            raise_on_status(status)
+        return out.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return grad_out * grad, None, None, None, None, None, None
+
+
+def loglik(locs, z, nbr, theta, nu: float, m: int, check: bool = True):
+    """Differentiable Vecchia log-likelihood (0-d float64 tensor on the device).
+
+    check=True synchronises once to raise VecchiaNumericalError on a failed
+    conditional; pass False inside captured graphs or tight loops and read the
+    status yourself."""
+    return VecchiaLogLik.apply(theta, locs, z, nbr, float(nu), int(m), check)
