@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=120)
+    ap.add_argument("--variant", default="auto", help="kernel variant (auto, unblocked, tile_w1/2/4/8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -112,7 +113,8 @@ def main():
     ws = torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev)
 
     def step():
-        v.vecchia_loglik_grad(locs, z, nbr, f.m, f.nu, theta, out=out, grad=grad, status=status, ws=ws)
+        v.vecchia_loglik_variant(locs, z, nbr, f.m, f.nu, theta, args.variant, with_grad=True, out=out, grad=grad,
+                                 status=status, ws=ws)
 
     for _ in range(args.warmup):
         step()
@@ -153,7 +155,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name} value+gradient", "n": f.n, "m": f.m, "nu": f.nu,
-                   "theta": [float(x) for x in f.thetas[0]], "form": "plain"},
+                   "theta": [float(x) for x in f.thetas[0]], "form": "plain",
+                   "variant": args.variant if args.variant != "auto" else v.vecchia_get_variant(f.m, True)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "algorithmic_flops_per_launch": flops, "kernel_evals_per_launch": evals,

@@ -110,12 +110,64 @@ int vecchia_loglik_grad(const double *locs, const double *z, const int32_t *nbr,
  *          points (then nidx must equal n)
  *   terms  [dev] double[nidx]      l_i for idx[t]
  *   gterms [dev] double[nidx][3]   dl_i/d(sigma2, beta, tau2), or NULL
- *   status [dev] int64[1]          as above, over the listed points
- * An index outside [0, n) in idx marks status with t + 1 and yields NaN.
+ *   status [dev] int64[1]          0; VECCHIA_STATUS_THETA; or t + 1 for the
+ *                                  smallest position t whose point failed (as
+ *                                  above) or whose index idx[t] is outside [0, n)
+ * Failed positions hold NaN.
  */
 int vecchia_loglik_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                          double nu, const double *theta, const int64_t *idx, int64_t nidx, double *terms,
                          double *gterms, int64_t *status, void *stream);
+
+/*
+ * Kernel variants.  Every variant evaluates the same conditionals (Algorithm 1
+ * fused per point); they differ in how a workgroup maps onto one conditional:
+ *   VECCHIA_VARIANT_UNBLOCKED  256 threads, the block packed in LDS, unblocked
+ *                              right-looking Cholesky;
+ *   VECCHIA_VARIANT_TILE_W{1,2,4,8}
+ *                              the block as 16x16 register tiles over 1, 2, 4
+ *                              or 8 wavefronts, Cholesky blocked by tile columns
+ *                              with FP64 matrix-core trailing updates.
+ * VECCHIA_VARIANT_AUTO uses the per-(m, gradient) table below, or a built-in
+ * default.  A tile variant is feasible when each wavefront holds at most 20
+ * tiles; vecchia_variant_feasible reports it.
+ */
+enum vecchia_variant {
+    VECCHIA_VARIANT_AUTO = 0,
+    VECCHIA_VARIANT_UNBLOCKED = 1,
+    VECCHIA_VARIANT_TILE_W1 = 2,
+    VECCHIA_VARIANT_TILE_W2 = 3,
+    VECCHIA_VARIANT_TILE_W4 = 4,
+    VECCHIA_VARIANT_TILE_W8 = 5
+};
+
+/* 1 if `variant` can run conditioning sets of size m, else 0. */
+int vecchia_variant_feasible(int32_t m, int32_t variant);
+
+/*
+ * Sets the variant used by the entry points above for size m (0..VECCHIA_MAX_M)
+ * with (with_grad != 0) or without the gradient; VECCHIA_VARIANT_AUTO restores
+ * the default.  This host-side table is the library's only state; an
+ * autotuner fills it.  Not thread-safe against concurrent launches.
+ * Returns VECCHIA_OK, VECCHIA_EINVAL or VECCHIA_EUNSUPPORTED (infeasible).
+ */
+int vecchia_set_variant(int32_t m, int32_t with_grad, int32_t variant);
+
+/* The variant the entry points use for (m, with_grad); negative on bad m. */
+int vecchia_get_variant(int32_t m, int32_t with_grad);
+
+/*
+ * vecchia_loglik (grad == NULL) or vecchia_loglik_grad (grad != NULL) with an
+ * explicit variant; same arguments and results otherwise.
+ */
+int vecchia_loglik_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                           double nu, const double *theta, int32_t variant, double *out, double *grad,
+                           int64_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* vecchia_loglik_terms with an explicit variant. */
+int vecchia_loglik_terms_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                                 double nu, const double *theta, int32_t variant, const int64_t *idx,
+                                 int64_t nidx, double *terms, double *gterms, int64_t *status, void *stream);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libvecchia.so")
 
 VECCHIA_MAX_M = 160
 VECCHIA_STATUS_THETA = -1
+VARIANTS = {"auto": 0, "unblocked": 1, "tile_w1": 2, "tile_w2": 3, "tile_w4": 4, "tile_w8": 5}
 _ERRORS = {1: "VECCHIA_EINVAL", 2: "VECCHIA_EUNSUPPORTED", 3: "VECCHIA_EHIP", 4: "VECCHIA_EWORKSPACE"}
 
 _lib = None
@@ -74,6 +75,16 @@ def _load():
         lib.vecchia_loglik_grad.argtypes = [P, P, P, I64, I32, D, P, P, P, P, P, SZ, P]
         lib.vecchia_loglik_terms.restype = ctypes.c_int
         lib.vecchia_loglik_terms.argtypes = [P, P, P, I64, I32, D, P, P, I64, P, P, P, P]
+        lib.vecchia_variant_feasible.restype = ctypes.c_int
+        lib.vecchia_variant_feasible.argtypes = [I32, I32]
+        lib.vecchia_set_variant.restype = ctypes.c_int
+        lib.vecchia_set_variant.argtypes = [I32, I32, I32]
+        lib.vecchia_get_variant.restype = ctypes.c_int
+        lib.vecchia_get_variant.argtypes = [I32, I32]
+        lib.vecchia_loglik_variant.restype = ctypes.c_int
+        lib.vecchia_loglik_variant.argtypes = [P, P, P, I64, I32, D, P, I32, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_terms_variant.restype = ctypes.c_int
+        lib.vecchia_loglik_terms_variant.argtypes = [P, P, P, I64, I32, D, P, I32, P, I64, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -182,6 +193,64 @@ def vecchia_loglik_terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_
                                       _ptr(theta), _ptr(idx), nidx, _ptr(terms), _ptr(gterms), _ptr(status),
                                       _stream(stream))
     _check(rc, "vecchia_loglik_terms")
+    return terms[:nidx], (gterms[:nidx] if gterms is not None else None), status
+
+
+def _variant_id(variant) -> int:
+    return VARIANTS[variant] if isinstance(variant, str) else int(variant)
+
+
+def vecchia_variant_feasible(m: int, variant) -> bool:
+    return bool(_load().vecchia_variant_feasible(int(m), _variant_id(variant)))
+
+
+def vecchia_set_variant(m: int, with_grad: bool, variant) -> None:
+    _check(_load().vecchia_set_variant(int(m), int(bool(with_grad)), _variant_id(variant)), "vecchia_set_variant")
+
+
+def vecchia_get_variant(m: int, with_grad: bool) -> int:
+    return int(_load().vecchia_get_variant(int(m), int(bool(with_grad))))
+
+
+def vecchia_loglik_variant(locs, z, nbr, m: int, nu: float, theta, variant, with_grad: bool = False, out=None,
+                           grad=None, status=None, ws=None, stream=None):
+    """vecchia_loglik / vecchia_loglik_grad with an explicit kernel variant; returns (out, grad|None, status)."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    if with_grad and grad is None:
+        grad = torch.empty(3, dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
+    _dev_check(theta, out, grad if with_grad else None, status)
+    ws = _workspace(n, m, dev, ws)
+    rc = _load().vecchia_loglik_variant(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
+                                        _ptr(theta), _variant_id(variant), _ptr(out),
+                                        _ptr(grad) if with_grad else None, _ptr(status), _ptr(ws), ws.numel(),
+                                        _stream(stream))
+    _check(rc, "vecchia_loglik_variant")
+    return out, (grad if with_grad else None), status
+
+
+def vecchia_loglik_terms_variant(locs, z, nbr, m: int, nu: float, theta, variant, idx=None, with_grad=False,
+                                 stream=None):
+    """vecchia_loglik_terms with an explicit kernel variant."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    if idx is not None:
+        if idx.dtype != torch.int64:
+            raise TypeError("idx must be int64")
+        _dev_check(idx)
+        nidx = idx.shape[0]
+    else:
+        nidx = n
+    terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
+    gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
+    status = torch.empty(1, dtype=torch.int64, device=dev)
+    _dev_check(theta)
+    rc = _load().vecchia_loglik_terms_variant(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
+                                              _ptr(theta), _variant_id(variant), _ptr(idx), nidx, _ptr(terms),
+                                              _ptr(gterms), _ptr(status), _stream(stream))
+    _check(rc, "vecchia_loglik_terms_variant")
     return terms[:nidx], (gterms[:nidx] if gterms is not None else None), status
 
 

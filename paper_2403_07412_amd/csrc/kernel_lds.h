@@ -42,7 +42,7 @@ __host__ __device__ inline size_t lds_kernel_smem_bytes(int m) {
 }
 
 template <int NU, bool GRAD>
-__device__ CondOut lds_conditional(const double *__restrict__ locs, const double *__restrict__ z,
+__device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ locs, const double *__restrict__ z,
                                    const int32_t *__restrict__ nbr, int64_t i, int32_t m, const Params &P,
                                    double *smem) {
     constexpr int NT = 256;

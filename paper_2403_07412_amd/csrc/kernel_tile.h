@@ -1,0 +1,428 @@
+// Tiled kernel: one workgroup of W wavefronts per conditional, the augmented
+// block held in registers as 16x16 tiles, the Cholesky blocked by tile
+// columns with its trailing updates on FP64 matrix cores.
+//
+// Block layout (same augmented block as the unblocked kernel): rows 0..k-1
+// neighbours, row k the point itself, row k+1 the observations, rows k+2..
+// 16T-1 identity padding.  Factoring rows 0..k gives L_kk^2 = c_i and, in row
+// k+1, the two forward solves of Algorithm 1 (POTRF + 2 TRSV, fused).
+//
+// Register tiles.  v_mfma_f64_16x16x4f64 leaves D[4r + l/16][l%16] in
+// accumulator register r of lane l.  Every tile M of the block is kept in
+// the transposed form of that layout ("T-layout"): lane (g, j) = (l/16, l%16),
+// register r holds M[j][4r + g].  With the inner index of a product taken as
+// kk = 4s + g in instruction s, a T-layout tile is directly the B operand of
+// M' M^T-style products and the panel operands need no transposes:
+//   TRSM  X^T = Linv A^T     A operand Linv[m][4s+g] (Linv in T-layout),
+//                            B operand register s of the tile itself;
+//   SYRK  A^T -= X_C X_R^T   both operands register s of the panel tiles.
+// The result of each product lands again in T-layout.
+//
+// Per tile column t:
+//   1. the owner of the diagonal tile factors it (16 columns, one row per lane,
+//      64-bit DPP row broadcasts) and forms its inverse Linv_t (columns split
+//      over the four lane groups, which yields Linv_t in T-layout directly);
+//   2. owners of the tiles below apply X = A Linv_t^T (4 MFMAs per tile) and
+//      publish X to the LDS panel;
+//   3. owners of the trailing tiles subtract X_R X_C^T (4 MFMAs per tile).
+// Gradient: the same back substitution as the unblocked kernel, by tiles:
+//   x_t = Linv_t^T q_t, then q_C -= L_tC^T x_t for the tiles left of t.
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.h"
+#include "kernel_lds.h"
+
+namespace vecchia {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int tile_count(int T) { return T * (T + 1) / 2; }
+__host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_count(T) + W - 1) / W; }
+
+// Occupancy target (wavefronts per SIMD) the register allocation aims at: as
+// many workgroups per CU as the LDS of one conditional allows, at most 4.
+__host__ __device__ constexpr int tile_waves_per_simd(int T, int W) {
+    // LDS doubles per workgroup (mirrors TileLds<T>::TOTAL)
+    const int lds = (2 * T * 256 + 272 + 9 * 16 * T + 32) * 8;
+    int blocks = 163840 / lds;
+    int wps = (blocks * W) / 4;
+    if (wps < 1) wps = 1;
+    if (wps > 4) wps = 4;
+    return wps;
+}
+
+// LDS layout of the tiled kernel, in doubles.
+template <int T>
+struct TileLds {
+    static constexpr int KP = 16 * T;
+    static constexpr int LINV = 0;                  // [T][64 lanes][4]   inverse diagonal tiles, T-layout
+    static constexpr int PANEL = LINV + T * 256;    // [T][64 lanes][4]   current panel X_R, slot R
+    static constexpr int DIAG = PANEL + T * 256;    // [16][17]           diagonal tile, row-major
+    static constexpr int XY = DIAG + 272;           // [KP][2]            coordinates
+    static constexpr int ZV = XY + 2 * KP;          // [KP]               observations
+    static constexpr int YP = ZV + KP;              // [KP]               factor row k+1
+    static constexpr int Q1 = YP + KP;              // [KP]               back-substitution vectors
+    static constexpr int Q2 = Q1 + KP;
+    static constexpr int U = Q2 + KP;
+    static constexpr int BH = U + KP;
+    static constexpr int SCAL = BH + KP;            // [16]               scalars: [0] L_kk
+    static constexpr int RED = SCAL + 16;           // [16]               reductions
+    static constexpr int TOTAL = RED + 16;
+    static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
+};
+
+// Tile enumeration: column C descending, row R ascending inside a column, so
+// the tiles still active after step t form a prefix and a round-robin owner
+// assignment balances every step.
+__device__ inline void tile_rc(int T, int idx, int &R, int &C) {
+    int start = 0;
+    R = -1;
+    C = -1;
+    for (int c = T - 1; c >= 0; --c) {
+        const int cnt = T - c;
+        if (idx < start + cnt) {
+            C = c;
+            R = c + (idx - start);
+            return;
+        }
+        start += cnt;
+    }
+}
+
+__device__ inline int tile_index(int T, int R, int C) {
+    // tiles of columns T-1 .. C+1 come first
+    const int before = (T - 1 - C) * (T - C) / 2;
+    return before + (R - C);
+}
+
+template <int SRC>
+__device__ __forceinline__ double bcast_row(double v) {
+    // every lane of each 16-lane row receives lane SRC of that row (64-bit DPP row_newbcast)
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xF, 0xF, false);
+}
+
+// acc += v(lane SRC of this lane's row) * w, one fused 64-bit DPP FMA.  The
+// leading s_nop gives the two wait states a DPP source needs after a VALU
+// write (the compiler does not track hazards inside inline assembly).
+template <int SRC>
+__device__ __forceinline__ void fma_bcast_row(double &acc, double v, double w) {
+    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                 : "+v"(acc)
+                 : "v"(v), "v"(w), "i"(SRC));
+}
+
+// compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+__device__ __forceinline__ double rsqrt_refined(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y;
+}
+
+__device__ __forceinline__ double sum16(double v) {
+    // sum over the 16 lanes of a row; every lane of the row gets the result
+    v += __shfl_xor(v, 1, kWave);
+    v += __shfl_xor(v, 2, kWave);
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 8, kWave);
+    return v;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Covariance entry of the augmented block at (a, b); see the layout above.
+template <int NU>
+__device__ __forceinline__ double block_entry(int a, int b, int k, const double *__restrict__ XY,
+                                              const double *__restrict__ Z, const Params &P) {
+    const double r = dist2d(XY[2 * a], XY[2 * a + 1], XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
+    const double cov = matern_r<NU>(r, P.sigma2) + (a == b ? P.tau2 : 0.0);
+    const int hi = a > b ? a : b, lo = a > b ? b : a;
+    double v = cov;
+    if (hi == k + 1) v = (lo == k + 1) ? 1.0 : Z[lo];
+    if (hi > k + 1) v = (a == b) ? 1.0 : 0.0;
+    return v;
+}
+
+// Factors diagonal tile t, which the calling wave has stored row-major in the
+// DIAG area of LDS; publishes Linv_t (T-layout, lane-major) and records L_kk
+// and the part of factor row k+1 that falls in this tile.  Returns true on a
+// non-positive or non-finite pivot among rows <= k.
+template <int T>
+__device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
+    using Ls = TileLds<T>;
+    int l = threadIdx.x % kWave;
+    asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
+    const int g = l / 16, j = l % 16;
+    double *S = smem + Ls::DIAG;  // the caller stored the tile here, row-major with stride 17
+    wave_lds_sync();
+    double R[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) R[c] = S[j * 17 + c];
+    wave_lds_sync();
+
+    bool bad = false;
+    const int base = 16 * t;
+    const int jk = k - base;      // local index of row k (point i) if it lies in this tile
+    const int jy = k + 1 - base;  // local index of row k+1 (observations) if it lies in this tile
+    // Linv is built row by row alongside the factor: lane (g, j) keeps
+    // Linv[j][4r + g] (r = 0..3) in Wr, i.e. Linv in T-layout.
+    double Wr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wr[r] = (j == 4 * r + g) ? 1.0 : 0.0;
+    double dk = 0.0;
+    static_for<0, 16>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double piv = bcast_row<q>(R[q]);
+        double inv = 1.0, d = 1.0;
+        if (base + q <= k) {
+            bad |= !(piv > 0.0) || !isfinite(piv);
+            inv = rsqrt_refined(piv);
+            d = piv * inv;
+        }
+        if (q == jk) dk = d;
+        R[q] = (j > q) ? R[q] * inv : ((j == q) ? d : 0.0);  // column q of L
+        // row q of Linv is final: Linv[q][.] = W_q / L_qq; eliminate it from the rows below
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double bq = bcast_row<q>(Wr[r]) * inv;
+            Wr[r] = (j == q) ? bq : ((j > q) ? fma(-R[q], bq, Wr[r]) : Wr[r]);
+        }
+        // trailing update of the tile: R[c] -= L[j][q] L[c][q], L[c][q] broadcast from lane c
+        const double nRq = -R[q];
+        static_for<q + 1, 16>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            fma_bcast_row<c>(R[c], R[q], nRq);
+        });
+    });
+    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = dk;
+    if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < jy) smem[Ls::YP + base + c] = R[c];
+    }
+    double *Li = smem + Ls::LINV + t * 256 + l * 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Li[r] = Wr[r];
+    return bad;
+}
+
+template <int T, int W, int NU, bool GRAD>
+__device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ locs, const double *__restrict__ z,
+                                    const int32_t *__restrict__ nbr, int64_t i, int32_t m, const Params &P,
+                                    double *smem) {
+    using Ls = TileLds<T>;
+    constexpr int NT = W * kWave;
+    constexpr int NTW = tiles_per_wave(T, W);
+    constexpr int NTILES = tile_count(T);
+    constexpr int KP = Ls::KP;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int l = tid % kWave;
+    const int g = l / 16, j = l % 16;
+    const int k = (int)(i < m ? i : m);
+    double *XY = smem + Ls::XY;
+    double *Z = smem + Ls::ZV;
+    bool bad = false;
+
+    // my tiles: slot s holds tile index w + W s; (R, C) packed as R * 32 + C, -1 if unused
+    int sRC[NTW];
+#pragma unroll
+    for (int s = 0; s < NTW; ++s) {
+        const int idx = w + W * s;
+        int R_ = -1, C_ = -1;
+        if (idx < NTILES) tile_rc(T, idx, R_, C_);
+        sRC[s] = (R_ < 0) ? -1 : R_ * 32 + C_;
+    }
+#define SR(s) (sRC[s] < 0 ? -1 : (sRC[s] >> 5))
+#define SC(s) (sRC[s] < 0 ? -1 : (sRC[s] & 31))
+
+    __syncthreads();  // the previous conditional is done with smem
+    // gather (Algorithm 1: s_{J_i}, y_{J_i}); indices are checked before use
+    for (int t = tid; t < KP; t += NT) {
+        double x = 0.0, y = 0.0, zz = 0.0;
+        if (t <= k) {
+            int64_t jj = i;
+            if (t < k) {
+                const int32_t jn = nbr[i * (int64_t)m + t];
+                const bool okj = (jn >= 0) && ((int64_t)jn < i);
+                bad |= !okj;
+                jj = okj ? (int64_t)jn : 0;
+            }
+            const double2 p = *reinterpret_cast<const double2 *>(locs + 2 * jj);
+            x = p.x;
+            y = p.y;
+            zz = z[jj];
+        }
+        XY[2 * t] = x;
+        XY[2 * t + 1] = y;
+        Z[t] = zz;
+    }
+    __syncthreads();
+
+    // covariance generation straight into the register tiles
+    dvec4 tile[NTW];
+#pragma unroll
+    for (int s = 0; s < NTW; ++s) {
+        if (SR(s) >= 0) {
+            const int a = 16 * SR(s) + j;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[s][r] = block_entry<NU>(a, 16 * SC(s) + 4 * r + g, k, XY, Z, P);
+        } else {
+            tile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
+        }
+    }
+
+    // blocked right-looking Cholesky
+#pragma unroll 1
+    for (int t = 0; t < T; ++t) {
+        // 1. diagonal tile t (already fully updated by its owner)
+        const int own_d = tile_index(T, t, t) % W;
+        if (w == own_d) {
+            const int sd = tile_index(T, t, t) / W;
+#pragma unroll
+            for (int s = 0; s < NTW; ++s) {
+                if (s == sd) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) smem[Ls::DIAG + j * 17 + 4 * r + g] = tile[s][r];
+                }
+            }
+            bad |= factor_diag<T>(t, k, smem);
+        }
+        __syncthreads();
+        // 2. tiles below: X = A Linv_t^T, published to the panel
+        const double *Li = smem + Ls::LINV + t * 256 + l * 4;
+#pragma unroll
+        for (int s = 0; s < NTW; ++s) {
+            if (SC(s) == t && SR(s) > t) {
+                const dvec4 li = *reinterpret_cast<const dvec4 *>(Li);
+                dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
+                tile[s] = acc;
+                *reinterpret_cast<dvec4 *>(smem + Ls::PANEL + SR(s) * 256 + l * 4) = acc;
+            }
+        }
+        __syncthreads();
+        // 3. trailing update of the tiles right of column t
+#pragma unroll
+        for (int s = 0; s < NTW; ++s) {
+            if (SC(s) > t) {
+                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::PANEL + SR(s) * 256 + l * 4);
+                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::PANEL + SC(s) * 256 + l * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xc[q], xr[q], tile[s], 0, 0, 0);
+            }
+        }
+    }
+    // observation row k+1 from the tiles left of its diagonal tile
+    const int ty = (k + 1) / 16, jy = (k + 1) % 16;
+#pragma unroll
+    for (int s = 0; s < NTW; ++s) {
+        if (SR(s) == ty && SC(s) < ty && j == jy) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) smem[Ls::YP + 16 * SC(s) + 4 * r + g] = tile[s][r];
+        }
+    }
+    __syncthreads();
+
+    CondOut o;
+    const double Lkk = smem[Ls::SCAL + 0];
+    const double wv = smem[Ls::YP + k];
+    o.ell = -0.5 * (kLog2Pi + 2.0 * log(Lkk) + wv * wv);
+    o.g0 = o.g1 = o.g2 = 0.0;
+
+    if constexpr (GRAD) {
+        const double c = Lkk * Lkk;
+        const double rr = wv / Lkk;
+        const double half = 0.5 * (rr * rr - 1.0 / c);
+        double *Q1 = smem + Ls::Q1, *Q2 = smem + Ls::Q2, *U = smem + Ls::U, *BH = smem + Ls::BH;
+        const double *YP = smem + Ls::YP;
+        for (int t = tid; t < KP; t += NT) {
+            Q1[t] = (t < k) ? rr * YP[t] : (t == k ? half * Lkk : 0.0);
+            Q2[t] = (t == k) ? Lkk : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int t = T - 1; t >= 0; --t) {
+            if (w == tile_index(T, t, t) % W) {
+                const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
+                const double q1 = Q1[16 * t + j], q2 = Q2[16 * t + j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double p1 = sum16(li[r] * q1);
+                    const double p2 = sum16(li[r] * q2);
+                    if (j == 0) {
+                        U[16 * t + 4 * r + g] = p1;
+                        BH[16 * t + 4 * r + g] = p2;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < NTW; ++s) {
+                if (SR(s) == t && SC(s) < t) {
+                    const double x1 = U[16 * t + j], x2 = BH[16 * t + j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double p1 = sum16(tile[s][r] * x1);
+                        const double p2 = sum16(tile[s][r] * x2);
+                        if (j == 0) {
+                            Q1[16 * SC(s) + 4 * r + g] -= p1;
+                            Q2[16 * SC(s) + 4 * r + g] -= p2;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // dl/dtau2 = u^T b; dl/dbeta = sum_{a > b} D_ab (u_a b_b + u_b b_a)
+        double ub = 0.0;
+        for (int t = tid; t <= k; t += NT) ub += U[t] * BH[t];
+        double gb = 0.0;
+        const double s2b = P.sigma2 * P.inv_beta;
+#pragma unroll
+        for (int s = 0; s < NTW; ++s) {
+            if (SR(s) >= 0) {
+                const int a = 16 * SR(s) + j;
+                const double ua = U[a], ba = BH[a], xa = XY[2 * a], ya = XY[2 * a + 1];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int b = 16 * SC(s) + 4 * r + g;
+                    if (a > b && a <= k) {
+                        const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
+                        gb += matern_dbeta_r<NU>(rb, s2b) * (ua * BH[b] + U[b] * ba);
+                    }
+                }
+            }
+        }
+        ub = block_sum<W>(ub, smem + Ls::RED);
+        gb = block_sum<W>(gb, smem + Ls::RED);
+        o.g2 = ub;
+        o.g0 = (0.5 * (rr * rr * c - 1.0) - P.tau2 * ub) / P.sigma2;
+        o.g1 = gb;
+    }
+    const bool anybad = __syncthreads_or(bad ? 1 : 0) != 0;
+    o.bad = anybad || !isfinite(o.ell) || !isfinite(o.g0) || !isfinite(o.g1) || !isfinite(o.g2);
+    return o;
+#undef SR
+#undef SC
+}
+
+}  // namespace vecchia

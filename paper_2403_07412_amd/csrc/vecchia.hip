@@ -1,120 +1,105 @@
 // C ABI and launch logic of the Vecchia log-likelihood library (gfx950).
 //
 // Pipeline of one evaluation (Algorithm 1, fused):
-//   conditional kernel  every workgroup takes a fixed chunk of kChunk points
-//                       and, point by point, gathers the neighbours, builds the
-//                       covariance block, factors it, solves, forms l_i (and
-//                       its gradient), and adds the results in ascending i into
-//                       one partial per chunk;
-//   finalize kernel     sums the partials in a fixed order with double-double
-//                       accumulation and writes l, the gradient and the status.
-// Chunk boundaries and both summation orders are fixed, so results are
-// bitwise reproducible whatever order the hardware runs the workgroups in.
+//   conditional kernel  one workgroup per point i: gathers the neighbours,
+//                       builds the covariance block, factors it, solves, forms
+//                       l_i (and its gradient) and writes the four values and
+//                       a failure flag for i;
+//   reduce kernel       every thread adds a fixed chunk of kChunk consecutive
+//                       points in ascending order; each workgroup combines its
+//                       threads' sums in a fixed tree (double-double);
+//   finalize kernel     sums the workgroup partials in a fixed order and writes
+//                       l, the gradient and the status.
+// All summation orders are fixed, so results are bitwise reproducible
+// whatever order the hardware runs the workgroups in.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 
-#include "../../include/vecchia.h"
-#include "device_common.h"
-#include "kernel_lds.h"
+#include "vecchia.h"
+#include "launch.h"
 
 using namespace vecchia;
 
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kFinalizeThreads = 256;
-
-int64_t num_chunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Workspace layout: partials [nchunks][4] double, then first failures [nchunks] int64.
+constexpr int kReduceThreads = 256;
+constexpr int64_t kPointsPerReduceBlock = (int64_t)kChunk * kReduceThreads;
+
+int64_t num_reduce_blocks(int64_t n) { return (n + kPointsPerReduceBlock - 1) / kPointsPerReduceBlock; }
+
+// Workspace layout: per-point values [n][4] double, per-point flags [n] int32,
+// then per-reduce-block partials [nb][4] double-double and first failures [nb] int64.
 struct WsLayout {
+    double *vals;
+    int32_t *flags;
     double *partial;
     int64_t *pfail;
     size_t bytes;
 };
 
 WsLayout ws_layout(void *ws, int64_t n) {
-    const int64_t nc = num_chunks(n);
+    const int64_t nb = num_reduce_blocks(n);
     WsLayout L;
-    const size_t pbytes = align256((size_t)nc * 4 * sizeof(double));
-    const size_t fbytes = align256((size_t)nc * sizeof(int64_t));
-    L.bytes = pbytes + fbytes + 256;
+    const size_t vbytes = align256((size_t)n * 4 * sizeof(double));
+    const size_t fbytes = align256((size_t)n * sizeof(int32_t));
+    const size_t pbytes = align256((size_t)nb * 8 * sizeof(double));  // double-double pairs
+    const size_t qbytes = align256((size_t)nb * sizeof(int64_t));
+    L.bytes = vbytes + fbytes + pbytes + qbytes + 256;
     char *base = (char *)ws;
-    L.partial = (double *)base;
-    L.pfail = (int64_t *)(base + pbytes);
+    L.vals = (double *)base;
+    L.flags = (int32_t *)(base + vbytes);
+    L.partial = (double *)(base + vbytes + fbytes);
+    L.pfail = (int64_t *)(base + vbytes + fbytes + pbytes);
     return L;
 }
 
-// ---------------------------------------------------------------- kernels
-template <int NU, bool GRAD>
-__global__ void __launch_bounds__(kThreads) chunk_kernel_lds(const double *__restrict__ locs,
-                                                             const double *__restrict__ z,
-                                                             const int32_t *__restrict__ nbr, int64_t n, int32_t m,
-                                                             const double *__restrict__ theta,
-                                                             double *__restrict__ partial,
-                                                             int64_t *__restrict__ pfail) {
-    extern __shared__ double smem[];
-    const Params P = load_params(theta);
-    if (!P.valid) return;  // uniform: the finalize kernel reports the bad parameters
-    const int64_t c = blockIdx.x;
-    const int64_t i0 = c * kChunk;
-    const int64_t i1 = (i0 + kChunk < n) ? i0 + kChunk : n;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int64_t fail = kNoFailure;
-    for (int64_t i = i0; i < i1; ++i) {
-        const CondOut o = lds_conditional<NU, GRAD>(locs, z, nbr, i, m, P, smem);
-        acc0 += o.ell;
-        acc1 += o.g0;
-        acc2 += o.g1;
-        acc3 += o.g2;
-        if (o.bad && fail == kNoFailure) fail = i + 1;
+// Level 1 of the fixed-order sum: thread c of the grid adds points
+// [c kChunk, (c+1) kChunk) in ascending order; each workgroup combines its
+// threads in a fixed tree (double-double) into partial[block].
+__global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const double *__restrict__ vals,
+                                                                const int32_t *__restrict__ flags, int64_t n,
+                                                                double *__restrict__ partial,
+                                                                int64_t *__restrict__ pfail) {
+    __shared__ DD sh[4][kReduceThreads];
+    __shared__ int64_t shf[kReduceThreads];
+    const int t = threadIdx.x;
+    const int64_t i0 = ((int64_t)blockIdx.x * kReduceThreads + t) * kChunk;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t f = kNoFailure;
+    for (int64_t i = i0; i < i0 + kChunk && i < n; ++i) {
+        a0 += vals[4 * i + 0];
+        a1 += vals[4 * i + 1];
+        a2 += vals[4 * i + 2];
+        a3 += vals[4 * i + 3];
+        if (flags[i] && f == kNoFailure) f = i + 1;
     }
-    if (threadIdx.x == 0) {
-        partial[4 * c + 0] = acc0;
-        partial[4 * c + 1] = acc1;
-        partial[4 * c + 2] = acc2;
-        partial[4 * c + 3] = acc3;
-        pfail[c] = fail;
+    sh[0][t] = DD{a0, 0.0};
+    sh[1][t] = DD{a1, 0.0};
+    sh[2][t] = DD{a2, 0.0};
+    sh[3][t] = DD{a3, 0.0};
+    shf[t] = f;
+    __syncthreads();
+    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sh[q][t] = dd_add(sh[q][t], sh[q][t + s]);
+            shf[t] = min(shf[t], shf[t + s]);
+        }
+        __syncthreads();
     }
-}
-
-template <int NU, bool GRAD>
-__global__ void __launch_bounds__(kThreads) terms_kernel_lds(const double *__restrict__ locs,
-                                                             const double *__restrict__ z,
-                                                             const int32_t *__restrict__ nbr, int64_t n, int32_t m,
-                                                             const double *__restrict__ theta,
-                                                             const int64_t *__restrict__ idx, int64_t nidx,
-                                                             double *__restrict__ terms,
-                                                             double *__restrict__ gterms,
-                                                             unsigned long long *__restrict__ status) {
-    extern __shared__ double smem[];
-    const Params P = load_params(theta);
-    for (int64_t t = blockIdx.x; t < nidx; t += gridDim.x) {
-        const int64_t i = idx ? idx[t] : t;
-        CondOut o;
-        bool bad = false;
-        if (!P.valid || i < 0 || i >= n) {
-            const double nan = __builtin_nan("");
-            o.ell = o.g0 = o.g1 = o.g2 = nan;
-            bad = P.valid;  // bad parameters are reported once by the status fix-up
-        } else {
-            o = lds_conditional<NU, GRAD>(locs, z, nbr, i, m, P, smem);
-            bad = o.bad;
-            if (bad) o.ell = o.g0 = o.g1 = o.g2 = __builtin_nan("");
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            partial[8 * blockIdx.x + 2 * q] = sh[q][0].hi;
+            partial[8 * blockIdx.x + 2 * q + 1] = sh[q][0].lo;
         }
-        if (threadIdx.x == 0) {
-            terms[t] = o.ell;
-            if (gterms) {
-                gterms[3 * t + 0] = o.g0;
-                gterms[3 * t + 1] = o.g1;
-                gterms[3 * t + 2] = o.g2;
-            }
-            if (bad) atomicMin(status, (unsigned long long)(t + 1));
-        }
+        pfail[blockIdx.x] = shf[0];
     }
 }
 
@@ -132,11 +117,11 @@ __global__ void status_fix_kernel(unsigned long long *status, const double *__re
     }
 }
 
-// Sums the chunk partials in a fixed order (strided per thread, then a fixed
-// tree) with double-double accumulation; writes l, the gradient and the status.
+// Level 2 of the fixed-order sum: the reduce-block partials (double-double)
+// in a fixed order; writes l, the gradient and the status.
 __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double *__restrict__ partial,
                                                                     const int64_t *__restrict__ pfail,
-                                                                    int64_t nchunks,
+                                                                    int64_t nblocks,
                                                                     const double *__restrict__ theta,
                                                                     double *__restrict__ out,
                                                                     double *__restrict__ grad,
@@ -148,9 +133,9 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double
     DD a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     int64_t f = kNoFailure;
     if (P.valid) {
-        for (int64_t c = t; c < nchunks; c += kFinalizeThreads) {
+        for (int64_t c = t; c < nblocks; c += kFinalizeThreads) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = dd_add(a[q], partial[4 * c + q]);
+            for (int q = 0; q < 4; ++q) a[q] = dd_add(a[q], DD{partial[8 * c + 2 * q], partial[8 * c + 2 * q + 1]});
             f = min(f, pfail[c]);
         }
     }
@@ -183,6 +168,15 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double
 }
 
 // ---------------------------------------------------------------- dispatch
+// host-side variant table, indexed by [with_grad][m]; 0 = default
+int g_variant[2][VECCHIA_MAX_M + 1] = {};
+
+int resolve_variant(int m, bool grad, int requested) {
+    int v = requested != V_AUTO ? requested : g_variant[grad ? 1 : 0][m];
+    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m);
+    return v;
+}
+
 int nu_code(double nu) {
     if (nu == 0.5) return 0;
     if (nu == 1.5) return 1;
@@ -190,31 +184,11 @@ int nu_code(double nu) {
     return -1;
 }
 
-template <typename K>
-hipError_t allow_smem(K kernel, size_t bytes) {
-    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
-template <int NU, bool GRAD>
-int launch_chunks_lds(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
-                      const double *theta, const WsLayout &L, hipStream_t s) {
-    const int64_t nc = num_chunks(n);
-    if (nc == 0) return VECCHIA_OK;
-    const size_t smem = lds_kernel_smem_bytes(m);
-    auto kern = chunk_kernel_lds<NU, GRAD>;
-    if (allow_smem(kern, smem) != hipSuccess) return VECCHIA_EHIP;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nc), dim3(kThreads), smem, s, locs, z, nbr, n, m, theta, L.partial,
-                       L.pfail);
-    return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
-}
-
-template <bool GRAD>
-int launch_chunks(int nc_, const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
-                  const double *theta, const WsLayout &L, hipStream_t s) {
-    switch (nc_) {
-        case 0: return launch_chunks_lds<0, GRAD>(locs, z, nbr, n, m, theta, L, s);
-        case 1: return launch_chunks_lds<1, GRAD>(locs, z, nbr, n, m, theta, L, s);
-        default: return launch_chunks_lds<2, GRAD>(locs, z, nbr, n, m, theta, L, s);
+int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s) {
+    switch (nuc) {
+        case 0: return launch_nu05(grad, variant, a, s);
+        case 1: return launch_nu15(grad, variant, a, s);
+        default: return launch_nu25(grad, variant, a, s);
     }
 }
 
@@ -232,36 +206,43 @@ int check_common(const double *locs, const double *z, const int32_t *nbr, int64_
 
 int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
             const double *theta, double *out, double *grad, int64_t *status, void *ws, size_t ws_bytes,
-            void *stream, bool with_grad) {
+            void *stream, bool with_grad, int variant) {
     int rc = check_common(locs, z, nbr, n, m, nu, theta);
     if (rc != VECCHIA_OK) return rc;
     if (!out || !status || (with_grad && !grad)) return VECCHIA_EINVAL;
     WsLayout L = ws_layout(ws, n);
     if (!ws || ws_bytes < L.bytes) return VECCHIA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    const int nc_ = nu_code(nu);
-    rc = with_grad ? launch_chunks<true>(nc_, locs, z, nbr, n, m, theta, L, s)
-                   : launch_chunks<false>(nc_, locs, z, nbr, n, m, theta, L, s);
+    EvalArgs a{locs, z, nbr, n, m, theta, nullptr, n, L.vals, 4, with_grad ? L.vals + 1 : nullptr, 4, L.flags,
+               nullptr};
+    if (!with_grad) {
+        // the gradient slots of vals stay unwritten; the reduction still reads them
+        if (n > 0 && hipMemsetAsync(L.vals, 0, (size_t)n * 4 * sizeof(double), s) != hipSuccess) return VECCHIA_EHIP;
+    }
+    rc = launch_any(nu_code(nu), with_grad, resolve_variant(m, with_grad, variant), a, s);
     if (rc != VECCHIA_OK) return rc;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, L.partial, L.pfail, num_chunks(n),
-                       theta, out, with_grad ? grad : nullptr, status);
+    const int64_t nb = num_reduce_blocks(n);
+    if (nb > 0)
+        hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)nb), dim3(kReduceThreads), 0, s, L.vals, L.flags, n,
+                           L.partial, L.pfail);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinalizeThreads), 0, s, L.partial, L.pfail, nb, theta, out,
+                       with_grad ? grad : nullptr, status);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
 
-template <int NU, bool GRAD>
-int launch_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
-                 const double *theta, const int64_t *idx, int64_t nidx, double *terms, double *gterms,
-                 int64_t *status, hipStream_t s) {
-    const size_t smem = lds_kernel_smem_bytes(m);
-    auto kern = terms_kernel_lds<NU, GRAD>;
-    if (allow_smem(kern, smem) != hipSuccess) return VECCHIA_EHIP;
+int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+              const double *theta, const int64_t *idx, int64_t nidx, double *terms, double *gterms,
+              int64_t *status, void *stream, int variant) {
+    int rc = check_common(locs, z, nbr, n, m, nu, theta);
+    if (rc != VECCHIA_OK) return rc;
+    if (nidx < 0 || !status || (nidx > 0 && !terms) || (!idx && nidx != n)) return VECCHIA_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
     unsigned long long *st = (unsigned long long *)status;
+    const bool g = gterms != nullptr;
+    EvalArgs a{locs, z, nbr, n, m, theta, idx, nidx, terms, 1, gterms, 3, nullptr, st};
     hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, s, st);
-    if (nidx > 0) {
-        const int64_t grid = std::min<int64_t>(nidx, 1 << 20);
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), smem, s, locs, z, nbr, n, m, theta, idx,
-                           nidx, terms, gterms, st);
-    }
+    rc = launch_any(nu_code(nu), g, resolve_variant(m, g, variant), a, s);
+    if (rc != VECCHIA_OK) return rc;
     hipLaunchKernelGGL(status_fix_kernel, dim3(1), dim3(64), 0, s, st, theta);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
@@ -292,31 +273,55 @@ size_t vecchia_workspace_size(int64_t n, int32_t m) {
 
 int vecchia_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                    const double *theta, double *out, int64_t *status, void *ws, size_t ws_bytes, void *stream) {
-    return run_sum(locs, z, nbr, n, m, nu, theta, out, nullptr, status, ws, ws_bytes, stream, false);
+    return run_sum(locs, z, nbr, n, m, nu, theta, out, nullptr, status, ws, ws_bytes, stream, false, V_AUTO);
 }
 
 int vecchia_loglik_grad(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                         const double *theta, double *out, double *grad, int64_t *status, void *ws,
                         size_t ws_bytes, void *stream) {
-    return run_sum(locs, z, nbr, n, m, nu, theta, out, grad, status, ws, ws_bytes, stream, true);
+    return run_sum(locs, z, nbr, n, m, nu, theta, out, grad, status, ws, ws_bytes, stream, true, V_AUTO);
 }
 
 int vecchia_loglik_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                          double nu, const double *theta, const int64_t *idx, int64_t nidx, double *terms,
                          double *gterms, int64_t *status, void *stream) {
-    int rc = check_common(locs, z, nbr, n, m, nu, theta);
-    if (rc != VECCHIA_OK) return rc;
-    if (nidx < 0 || !status || (nidx > 0 && !terms) || (!idx && nidx != n)) return VECCHIA_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    const bool g = gterms != nullptr;
-    switch (nu_code(nu)) {
-        case 0: return g ? launch_terms<0, true>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s)
-                         : launch_terms<0, false>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s);
-        case 1: return g ? launch_terms<1, true>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s)
-                         : launch_terms<1, false>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s);
-        default: return g ? launch_terms<2, true>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s)
-                          : launch_terms<2, false>(locs, z, nbr, n, m, theta, idx, nidx, terms, gterms, status, s);
-    }
+    return run_terms(locs, z, nbr, n, m, nu, theta, idx, nidx, terms, gterms, status, stream, V_AUTO);
+}
+
+int vecchia_set_variant(int32_t m, int32_t with_grad, int32_t variant) {
+    if (m < 0 || m > VECCHIA_MAX_M || variant < V_AUTO || variant > V_TILE_W8) return VECCHIA_EINVAL;
+    if (variant != V_AUTO && !variant_feasible(variant, m)) return VECCHIA_EUNSUPPORTED;
+    g_variant[with_grad ? 1 : 0][m] = variant;
+    return VECCHIA_OK;
+}
+
+int vecchia_get_variant(int32_t m, int32_t with_grad) {
+    if (m < 0 || m > VECCHIA_MAX_M) return -VECCHIA_EINVAL;
+    return resolve_variant(m, with_grad != 0, V_AUTO);
+}
+
+int vecchia_variant_feasible(int32_t m, int32_t variant) {
+    if (m < 0 || m > VECCHIA_MAX_M || variant <= V_AUTO || variant > V_TILE_W8) return 0;
+    return variant_feasible(variant, m) ? 1 : 0;
+}
+
+int vecchia_loglik_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                           double nu, const double *theta, int32_t variant, double *out, double *grad,
+                           int64_t *status, void *ws, size_t ws_bytes, void *stream) {
+    if (variant < V_AUTO || variant > V_TILE_W8) return VECCHIA_EINVAL;
+    if (variant != V_AUTO && m >= 0 && m <= VECCHIA_MAX_M && !variant_feasible(variant, m))
+        return VECCHIA_EUNSUPPORTED;
+    return run_sum(locs, z, nbr, n, m, nu, theta, out, grad, status, ws, ws_bytes, stream, grad != nullptr,
+                   variant);
+}
+
+int vecchia_loglik_terms_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                                 double nu, const double *theta, int32_t variant, const int64_t *idx, int64_t nidx,
+                                 double *terms, double *gterms, int64_t *status, void *stream) {
+    if (variant < V_AUTO || variant > V_TILE_W8) return VECCHIA_EINVAL;
+    if (variant != V_AUTO && m >= 0 && m <= VECCHIA_MAX_M && !variant_feasible(variant, m))
+        return VECCHIA_EUNSUPPORTED;
+    return run_terms(locs, z, nbr, n, m, nu, theta, idx, nidx, terms, gterms, status, stream, variant);
 }
 
 }  // extern "C"
