@@ -7,6 +7,14 @@ One step = one full evaluation of the log-likelihood and its gradient
 (every conditional: gather, covariance, Cholesky, solves, adjoint, sums).
 Inputs are resident in HBM before timing starts.
 
+Two forms are timed on the same inputs:
+  plain    one vecchia_loglik_grad call per step with the built-in default
+           kernel variant;
+  batched  the variant chosen by the autotuner for (m, gradient), a batched
+           plan over the field, captured once into a HIP graph; one graph
+           launch per step.
+`value` is the batched form; the plain figures are reported beside it.
+
 Prints one JSON line.  Extra objects:
   roofline      algorithmic FP64 flops of the conditional kernel per launch
                 divided by its measured launch duration, against the FP64 peak;
@@ -80,8 +88,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=120)
-    ap.add_argument("--variant", default="auto", help="kernel variant (auto, unblocked, tile_w1/2/4/8)")
+    ap.add_argument("--variant", default="auto", help="plain form: kernel variant (auto, unblocked, tile_w1/2/4/8)")
+    ap.add_argument("--form", default="both", choices=["both", "plain", "batched"])
+    ap.add_argument("--tune-sample", type=int, default=50000, help="points the autotuner times per variant")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, copy a 512 MiB device buffer once (a kernel of known traffic that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
+    ap.add_argument("--traffic-kib", type=float, nargs=2, default=None, metavar=("FETCH", "WRITE"),
+                    help="HBM KiB per launch of the conditional kernel (FETCH_SIZE, WRITE_SIZE), already scaled "
+                         "by the copy-probe factor, to report as roofline.traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's conditionals are independent and a multi-GPU run "
@@ -112,35 +128,59 @@ def main():
     status = torch.empty(1, dtype=torch.int64, device=dev)
     ws = torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev)
 
-    def step():
-        v.vecchia_loglik_variant(locs, z, nbr, f.m, f.nu, theta, args.variant, with_grad=True, out=out, grad=grad,
-                                 status=status, ws=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = int(status.item())
-    if st != 0:
-        raise RuntimeError(f"status {st}")
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
+
+    def timed(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            step()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        return wall, [a.elapsed_time(b) for a, b in ev]
+
+    results = {}
+    if args.form in ("both", "plain"):
+        def plain_step():
+            v.vecchia_loglik_variant(locs, z, nbr, f.m, f.nu, theta, args.variant, with_grad=True, out=out,
+                                     grad=grad, status=status, ws=ws)
+        wall, launch_ms = timed(plain_step, args.steps, args.warmup)
+        if int(status.item()) != 0:
+            raise RuntimeError(f"plain: status {int(status.item())}")
+        results["plain"] = (wall, launch_ms, out.item(), grad.cpu().numpy().copy(),
+                            args.variant if args.variant != "auto" else v.vecchia_get_variant(f.m, True))
+    if args.form in ("both", "batched"):
+        best, us = v.vecchia_autotune(locs, z, nbr, f.m, f.nu, theta, True, sample=args.tune_sample, reps=2)
+        print(f"# autotune m={f.m} grad: best variant {best}; us/point {us}", file=sys.stderr, flush=True)
+        plan = v.BatchedPlan([(locs, z, nbr, f.m)], 1, f.nu, True)
+        thetas = theta.reshape(1, 1, 3).contiguous()
+        b_out, b_grad, b_status = plan.outputs()
+        graph = plan.capture(thetas, b_out, b_grad, b_status)
+        wall, launch_ms = timed(lambda: graph.launch(stream), args.steps, args.warmup)
+        if int(b_status.reshape(-1)[0].item()) != 0:
+            raise RuntimeError(f"batched: status {int(b_status.reshape(-1)[0].item())}")
+        results["batched"] = (wall, launch_ms, b_out.reshape(-1)[0].item(), b_grad.reshape(3).cpu().numpy().copy(),
+                              plan.classes()[0][1])
+        graph.close()
+        plan.close()
+    for form, (wall, launch_ms, ell, g, var) in results.items():
+        print(f"# {form}: variant {var}; {args.steps} steps: wall {wall * 1e3 / args.steps:.3f} ms/step, events mean "
+              f"{np.mean(launch_ms):.3f} ms (min {min(launch_ms):.3f}); loglik {ell:.12e} grad {g}",
+              file=sys.stderr, flush=True)
+    main_form = "batched" if "batched" in results else "plain"
+    wall, launch_ms, _, _, variant = results[main_form]
     ms = float(np.mean(launch_ms))
-    print(f"# {args.steps} steps: wall {wall * 1e3 / args.steps:.3f} ms/step, events mean {ms:.3f} ms "
-          f"(min {min(launch_ms):.3f}); loglik {out.item():.12e} grad {grad.cpu().numpy()}",
-          file=sys.stderr, flush=True)
 
     flops, evals, gbytes = workload_counts(f.n, f.m, True)
     achieved = flops / (ms * 1e-3) / 1e12
     value = f.n * args.steps / wall
+    names = {val: k for k, val in v.VARIANTS.items()}
     rec = {
         "metric": METRIC,
         "value": value,
@@ -155,13 +195,26 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name} value+gradient", "n": f.n, "m": f.m, "nu": f.nu,
-                   "theta": [float(x) for x in f.thetas[0]], "form": "plain",
-                   "variant": args.variant if args.variant != "auto" else v.vecchia_get_variant(f.m, True)},
+                   "theta": [float(x) for x in f.thetas[0]], "form": main_form,
+                   "variant": names.get(variant, variant)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "algorithmic_flops_per_launch": flops, "kernel_evals_per_launch": evals,
                      "gather_bytes_per_launch": gbytes, "launch_ms": ms},
     }
+    if "plain" in results and main_form != "plain":
+        pw, pl, _, _, pv = results["plain"]
+        rec["plain"] = {"value": f.n * args.steps / pw, "ms_per_step": pw * 1e3 / args.steps,
+                        "launch_ms": float(np.mean(pl)), "variant": names.get(pv, pv)}
+    if args.traffic_kib is not None:
+        rec["roofline"]["traffic"] = (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
+    if args.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(f, True)
     print(json.dumps(rec), flush=True)

@@ -59,6 +59,7 @@ extern "C" {
 #endif
 
 #define VECCHIA_MAX_M 160
+#define VECCHIA_MAX_FIELDS 4096
 #define VECCHIA_STATUS_THETA (-1)
 
 enum vecchia_error {
@@ -168,6 +169,96 @@ int vecchia_loglik_variant(const double *locs, const double *z, const int32_t *n
 int vecchia_loglik_terms_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                                  double nu, const double *theta, int32_t variant, const int64_t *idx,
                                  int64_t nidx, double *terms, double *gterms, int64_t *status, void *stream);
+
+/* ------------------------------------------------------------------ batched
+ * Many parameter vectors and many fields of uneven n and m in one enqueue
+ * (not in the paper; it evaluates one theta of one field per call).
+ *
+ * A field (host struct; its arrays are device arrays, layouts as above):   */
+typedef struct vecchia_field {
+    const double *locs;   /* [dev] [n][2] */
+    const double *z;      /* [dev] [n]    */
+    const int32_t *nbr;   /* [dev] [n][m] */
+    int64_t n;            /* >= 0 */
+    int32_t m;            /* 0..VECCHIA_MAX_M */
+} vecchia_field;
+
+/* Opaque plan (host object) and captured graph. */
+typedef struct vecchia_plan vecchia_plan;
+typedef struct vecchia_graph vecchia_graph;
+
+/*
+ * Plans the evaluation of nf fields (1..VECCHIA_MAX_FIELDS) under ntheta
+ * parameter vectors each, at smoothness nu, with (with_grad != 0) or without
+ * the gradient.  Evaluation e = f * ntheta + q is field f under theta q.
+ * Fields are grouped by tile class ceil((m+2)/16); each class uses the kernel
+ * variant that the variant table (vecchia_set_variant / vecchia_autotune) holds
+ * for the largest m of the class.  The field arrays must stay valid while the
+ * plan is used.  This call allocates a small device table (a few bytes per
+ * field), creates one stream per extra class, and synchronises; it is not
+ * meant for capture.  Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED
+ * (m or nf too large) or VECCHIA_EHIP.
+ */
+int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
+                        vecchia_plan **plan);
+
+/* Workspace (bytes) vecchia_loglik_batched needs: 36 bytes per (field, theta,
+ * point) plus a little for partial sums; 0 for a NULL plan. */
+size_t vecchia_plan_workspace_size(const vecchia_plan *plan);
+
+/* Number of tile classes of the plan, and the tile rows, variant, field count
+ * and item count (points x thetas) of class c. */
+int vecchia_plan_num_classes(const vecchia_plan *plan);
+int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_rows, int32_t *variant,
+                            int32_t *nfields, int64_t *items);
+
+/* Releases the plan, its device table and streams.  Not during its use. */
+int vecchia_plan_destroy(vecchia_plan *plan);
+
+/*
+ * Evaluates every (field, theta) of the plan:
+ *   thetas [dev] double [nf][ntheta][3]   (sigma2, beta, tau2) per evaluation
+ *   out    [dev] double [nf][ntheta]      log-likelihoods
+ *   grad   [dev] double [nf][ntheta][3]   gradients (required iff the plan has them)
+ *   status [dev] int64  [nf][ntheta]      per evaluation, as in the header notes
+ *   ws     [dev] at least vecchia_plan_workspace_size(plan) bytes
+ * The tile classes run concurrently on the plan's streams, forked from and
+ * joined back into `stream` (which must not be the legacy null stream when
+ * there is more than one class); all work is ordered after prior work on
+ * `stream` and complete when later work on `stream` starts.  No allocation,
+ * no synchronisation, no memset: capturable.  Each evaluation's sum uses the
+ * same fixed order as vecchia_loglik, so with the same variant the results
+ * are bitwise equal to single calls.  A plan must not be used by two host
+ * threads at once.
+ */
+int vecchia_loglik_batched(const vecchia_plan *plan, const double *thetas, double *out, double *grad,
+                           int64_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Captures vecchia_loglik_batched with these arguments into a HIP graph on
+ * `stream` (not the null stream) and instantiates it.  Replays read the device
+ * arrays in place, so new parameter vectors are written into `thetas` between
+ * launches.  vecchia_batched_graph_launch replays it on `stream`.
+ */
+int vecchia_batched_graph_create(const vecchia_plan *plan, const double *thetas, double *out, double *grad,
+                                 int64_t *status, void *ws, size_t ws_bytes, void *stream, vecchia_graph **graph);
+int vecchia_batched_graph_launch(vecchia_graph *graph, void *stream);
+int vecchia_batched_graph_destroy(vecchia_graph *graph);
+
+/*
+ * Autotuner: times every feasible variant on the last `sample` points of
+ * `field` (points with full conditioning sets where possible), best of `reps`
+ * runs, with (with_grad != 0) or without the gradient, and stores the fastest
+ * in the variant table for (field->m, with_grad).
+ *   theta        [dev] double[3]
+ *   ws           [dev] at least 40 * field->n bytes
+ *   best         [host] receives the chosen variant
+ *   us_per_point [host] double[6] or NULL: microseconds per point for each
+ *                variant (index = variant; -1 if infeasible; [0] = the best)
+ * Synchronises the stream.  Returns VECCHIA_OK or an error code.
+ */
+int vecchia_autotune(const vecchia_field *field, double nu, int32_t with_grad, const double *theta, int64_t sample,
+                     int32_t reps, void *ws, size_t ws_bytes, void *stream, int32_t *best, double *us_per_point);
 
 #ifdef __cplusplus
 }

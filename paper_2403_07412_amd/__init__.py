@@ -35,6 +35,12 @@ _ERRORS = {1: "VECCHIA_EINVAL", 2: "VECCHIA_EUNSUPPORTED", 3: "VECCHIA_EHIP", 4:
 _lib = None
 
 
+class _Field(ctypes.Structure):
+    """Mirror of struct vecchia_field."""
+    _fields_ = [("locs", ctypes.c_void_p), ("z", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("m", ctypes.c_int32)]
+
+
 class VecchiaError(RuntimeError):
     """A synchronous error code returned by the C ABI."""
 
@@ -85,6 +91,29 @@ def _load():
         lib.vecchia_loglik_variant.argtypes = [P, P, P, I64, I32, D, P, I32, P, P, P, P, SZ, P]
         lib.vecchia_loglik_terms_variant.restype = ctypes.c_int
         lib.vecchia_loglik_terms_variant.argtypes = [P, P, P, I64, I32, D, P, I32, P, I64, P, P, P, P]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        lib.vecchia_plan_create.restype = ctypes.c_int
+        lib.vecchia_plan_create.argtypes = [ctypes.POINTER(_Field), I32, I32, D, I32, PP]
+        lib.vecchia_plan_workspace_size.restype = SZ
+        lib.vecchia_plan_workspace_size.argtypes = [P]
+        lib.vecchia_plan_num_classes.restype = ctypes.c_int
+        lib.vecchia_plan_num_classes.argtypes = [P]
+        lib.vecchia_plan_class_info.restype = ctypes.c_int
+        lib.vecchia_plan_class_info.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                                ctypes.POINTER(I32), ctypes.POINTER(I64)]
+        lib.vecchia_plan_destroy.restype = ctypes.c_int
+        lib.vecchia_plan_destroy.argtypes = [P]
+        lib.vecchia_loglik_batched.restype = ctypes.c_int
+        lib.vecchia_loglik_batched.argtypes = [P, P, P, P, P, P, SZ, P]
+        lib.vecchia_batched_graph_create.restype = ctypes.c_int
+        lib.vecchia_batched_graph_create.argtypes = [P, P, P, P, P, P, SZ, P, PP]
+        lib.vecchia_batched_graph_launch.restype = ctypes.c_int
+        lib.vecchia_batched_graph_launch.argtypes = [P, P]
+        lib.vecchia_batched_graph_destroy.restype = ctypes.c_int
+        lib.vecchia_batched_graph_destroy.argtypes = [P]
+        lib.vecchia_autotune.restype = ctypes.c_int
+        lib.vecchia_autotune.argtypes = [ctypes.POINTER(_Field), D, I32, P, I64, I32, P, SZ, P,
+                                         ctypes.POINTER(I32), ctypes.POINTER(D)]
         _lib = lib
     return _lib
 
@@ -290,3 +319,118 @@ def loglik(locs, z, nbr, theta, nu: float, m: int, check: bool = True):
     conditional; pass False inside captured graphs or tight loops and read the
     status yourself."""
     return VecchiaLogLik.apply(theta, locs, z, nbr, float(nu), int(m), check)
+
+
+# ------------------------------------------------------------------ batched
+def _field_struct(locs, z, nbr, m):
+    n = _as_inputs(locs, z, nbr, m)
+    return _Field(locs.data_ptr() if n else None, z.data_ptr() if n else None,
+                  nbr.data_ptr() if (m > 0 and n) else None, n, m)
+
+
+class BatchedPlan:
+    """vecchia_plan_* over a list of fields (each (locs, z, nbr, m) of device tensors), ntheta parameter
+    vectors per field.  Keeps references to the field tensors for the plan's lifetime."""
+
+    def __init__(self, fields, ntheta: int, nu: float, with_grad: bool):
+        self._fields = [tuple(f) for f in fields]
+        arr = (_Field * len(self._fields))(*[_field_struct(*f) for f in self._fields])
+        handle = ctypes.c_void_p()
+        _check(_load().vecchia_plan_create(arr, len(self._fields), int(ntheta), float(nu), int(bool(with_grad)),
+                                           ctypes.byref(handle)), "vecchia_plan_create")
+        self.handle = handle
+        self.nf, self.ntheta, self.nu, self.with_grad = len(self._fields), int(ntheta), float(nu), bool(with_grad)
+        self.device = self._fields[0][1].device
+        self.ws = torch.empty(max(1, int(_load().vecchia_plan_workspace_size(handle))), dtype=torch.uint8,
+                              device=self.device)
+
+    def classes(self):
+        """[(tile_rows, variant, nfields, items)] per tile class."""
+        out = []
+        for c in range(_load().vecchia_plan_num_classes(self.handle)):
+            T, var, nfc, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            _check(_load().vecchia_plan_class_info(self.handle, c, ctypes.byref(T), ctypes.byref(var),
+                                                   ctypes.byref(nfc), ctypes.byref(items)), "class_info")
+            out.append((T.value, var.value, nfc.value, items.value))
+        return out
+
+    def outputs(self):
+        dev = self.device
+        out = torch.empty((self.nf, self.ntheta), dtype=torch.float64, device=dev)
+        grad = torch.empty((self.nf, self.ntheta, 3), dtype=torch.float64, device=dev) if self.with_grad else None
+        status = torch.empty((self.nf, self.ntheta), dtype=torch.int64, device=dev)
+        return out, grad, status
+
+    def __call__(self, thetas, out=None, grad=None, status=None, stream=None):
+        """vecchia_loglik_batched: thetas [nf][ntheta][3] float64 device tensor -> (out, grad|None, status)."""
+        if tuple(thetas.shape) != (self.nf, self.ntheta, 3) or thetas.dtype != torch.float64:
+            raise ValueError("thetas must be float64 [nf][ntheta][3]")
+        o, g, st = self.outputs()
+        out = o if out is None else out
+        grad = (g if grad is None else grad) if self.with_grad else None
+        status = st if status is None else status
+        _dev_check(thetas, out, grad, status)
+        rc = _load().vecchia_loglik_batched(self.handle, _ptr(thetas), _ptr(out), _ptr(grad), _ptr(status),
+                                            _ptr(self.ws), self.ws.numel(), _stream(stream))
+        _check(rc, "vecchia_loglik_batched")
+        return out, grad, status
+
+    def capture(self, thetas, out, grad, status, stream=None):
+        """vecchia_batched_graph_create on a side stream; returns a BatchedGraph bound to these arrays."""
+        _dev_check(thetas, out, grad, status)
+        s = stream if stream is not None else torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        handle = ctypes.c_void_p()
+        rc = _load().vecchia_batched_graph_create(self.handle, _ptr(thetas), _ptr(out), _ptr(grad), _ptr(status),
+                                                  _ptr(self.ws), self.ws.numel(), ctypes.c_void_p(s.cuda_stream),
+                                                  ctypes.byref(handle))
+        _check(rc, "vecchia_batched_graph_create")
+        return BatchedGraph(handle, self, (thetas, out, grad, status))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load().vecchia_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedGraph:
+    """A captured, instantiated batched evaluation; launch() replays it (reads thetas in place)."""
+
+    def __init__(self, handle, plan, keep):
+        self.handle, self._plan, self._keep = handle, plan, keep
+
+    def launch(self, stream=None):
+        _check(_load().vecchia_batched_graph_launch(self.handle, _stream(stream)), "vecchia_batched_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load().vecchia_batched_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vecchia_autotune(locs, z, nbr, m: int, nu: float, theta, with_grad: bool, sample: int = 20000, reps: int = 3,
+                     stream=None):
+    """Times every feasible variant for (m, with_grad) on these inputs, stores the fastest in the variant
+    table and returns (best_variant, {variant: microseconds per point})."""
+    f = _field_struct(locs, z, nbr, m)
+    ws = torch.empty(max(1, 40 * f.n), dtype=torch.uint8, device=z.device)
+    best = ctypes.c_int32()
+    us = (ctypes.c_double * 6)()
+    _dev_check(theta)
+    rc = _load().vecchia_autotune(ctypes.byref(f), float(nu), int(bool(with_grad)), _ptr(theta), int(sample),
+                                  int(reps), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(best), us)
+    _check(rc, "vecchia_autotune")
+    names = {v: k for k, v in VARIANTS.items()}
+    return best.value, {names[v]: us[v] for v in range(1, 6) if us[v] >= 0}

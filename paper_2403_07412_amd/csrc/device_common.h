@@ -30,11 +30,55 @@ __device__ inline Params load_params(const double *__restrict__ theta) {
     return p;
 }
 
+// e^{-r} for r >= 0.  Range reduction x = -r = k ln2 + f with |f| <= ln2/2
+// (ln2 split into a head with trailing zero bits and a tail, so k*ln2_head is
+// exact), e^f by its Taylor polynomial of degree 13 (truncation below 6e-18
+// relative), then scaling by 2^k.  Results below the double range flush to
+// 0; NaN propagates.  About 19 instructions, no table.
+__device__ __forceinline__ double exp_neg(double r) {
+    double x = -r;
+    x = (x < -745.5) ? -745.5 : x;  // keeps NaN (the comparison is false)
+    const double k = __builtin_rint(x * 1.4426950408889634074);
+    double f = fma(k, -6.93147180369123816490e-01, x);
+    f = fma(k, -1.90821492927058770002e-10, f);
+    double p = 1.0 / 6227020800.0;          // 1/13!
+    p = fma(p, f, 1.0 / 479001600.0);       // 1/12!
+    p = fma(p, f, 1.0 / 39916800.0);        // 1/11!
+    p = fma(p, f, 1.0 / 3628800.0);         // 1/10!
+    p = fma(p, f, 1.0 / 362880.0);          // 1/9!
+    p = fma(p, f, 1.0 / 40320.0);           // 1/8!
+    p = fma(p, f, 1.0 / 5040.0);            // 1/7!
+    p = fma(p, f, 1.0 / 720.0);             // 1/6!
+    p = fma(p, f, 1.0 / 120.0);             // 1/5!
+    p = fma(p, f, 1.0 / 24.0);              // 1/4!
+    p = fma(p, f, 1.0 / 6.0);               // 1/3!
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)k);
+}
+
+// sqrt(s) for a squared distance s >= 0: hardware reciprocal square root and
+// two coupled Newton (Goldschmidt) refinements of sqrt and 1/(2 sqrt), as in
+// a correctly rounded software sqrt, without the denormal rescaling: s below
+// 1e-290 (coincident points up to 1e-145) gives 0.  NaN propagates.
+__device__ __forceinline__ double sqrt_dist(double s) {
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y;
+    double h = 0.5 * y;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, s);
+    g = fma(d, h, g);
+    return (s > 1e-290) ? g : ((s >= 0.0) ? 0.0 : s);
+}
+
 // Matern covariance, Eq. (2), for half-integer smoothness in closed form.
 // NU: 0 -> nu = 0.5, 1 -> nu = 1.5, 2 -> nu = 2.5.  r = distance / beta.
 template <int NU>
 __device__ __forceinline__ double matern_r(double r, double sigma2) {
-    double e = exp(-r);
+    double e = exp_neg(r);
     if constexpr (NU == 0) {
         return sigma2 * e;
     } else if constexpr (NU == 1) {
@@ -48,7 +92,7 @@ __device__ __forceinline__ double matern_r(double r, double sigma2) {
 //   h = r e^-r (nu = 0.5), r^2 e^-r (nu = 1.5), r^2 (1 + r) e^-r / 3 (nu = 2.5).
 template <int NU>
 __device__ __forceinline__ double matern_dbeta_r(double r, double sigma2_over_beta) {
-    double e = exp(-r);
+    double e = exp_neg(r);
     if constexpr (NU == 0) {
         return sigma2_over_beta * (r * e);
     } else if constexpr (NU == 1) {
@@ -62,7 +106,7 @@ __device__ __forceinline__ double matern_dbeta_r(double r, double sigma2_over_be
 template <int NU>
 __device__ __forceinline__ void matern_and_dbeta_r(double r, double sigma2, double sigma2_over_beta, double &c,
                                                    double &db) {
-    double e = exp(-r);
+    double e = exp_neg(r);
     if constexpr (NU == 0) {
         c = sigma2 * e;
         db = sigma2_over_beta * (r * e);
@@ -78,7 +122,7 @@ __device__ __forceinline__ void matern_and_dbeta_r(double r, double sigma2, doub
 __device__ __forceinline__ double dist2d(double ax, double ay, double bx, double by) {
     double dx = ax - bx;
     double dy = ay - by;
-    return sqrt(dx * dx + dy * dy);
+    return sqrt_dist(fma(dx, dx, dy * dy));
 }
 
 // Sum over the 64 lanes of a wavefront; fixed butterfly order, every lane gets the total.

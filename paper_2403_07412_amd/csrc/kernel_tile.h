@@ -38,18 +38,28 @@ namespace vecchia {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
+#ifndef VECCHIA_KEEP_DBETA
+#define VECCHIA_KEEP_DBETA 1
+#endif
+
 __host__ __device__ constexpr int tile_count(int T) { return T * (T + 1) / 2; }
 __host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_count(T) + W - 1) / W; }
 
-// Occupancy target (wavefronts per SIMD) the register allocation aims at: as
-// many workgroups per CU as the LDS of one conditional allows, at most 4.
-__host__ __device__ constexpr int tile_waves_per_simd(int T, int W) {
-    // LDS doubles per workgroup (mirrors TileLds<T>::TOTAL)
-    const int lds = (2 * T * 256 + 272 + 9 * 16 * T + 32) * 8;
-    int blocks = 163840 / lds;
-    int wps = (blocks * W) / 4;
+// Occupancy target (wavefronts per SIMD) the register allocation aims at.
+// Workgroups per CU are limited by LDS and by registers: each lane holds 8
+// VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 88
+// for the diagonal factorisation and addressing.
+__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d) {
+    const int lds = (2 * T * 256 + 272 + 9 * 16 * T + 32) * 8;  // mirrors TileLds<T>::TOTAL
+    const int blocks_lds = 163840 / lds;
+    const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 88;
+    const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
+    const int blocks_regs = (wps_regs * 4) / W;      // workgroups per CU the registers allow
+    int blocks = blocks_lds < blocks_regs ? blocks_lds : blocks_regs;
+    if (blocks < 1) blocks = 1;
+    int wps = (blocks * W + 3) / 4;
     if (wps < 1) wps = 1;
-    if (wps > 4) wps = 4;
+    if (wps > 8) wps = 8;
     return wps;
 }
 
@@ -146,14 +156,12 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Covariance entry of the augmented block at (a, b); see the layout above.
-template <int NU>
-__device__ __forceinline__ double block_entry(int a, int b, int k, const double *__restrict__ XY,
-                                              const double *__restrict__ Z, const Params &P) {
-    const double r = dist2d(XY[2 * a], XY[2 * a + 1], XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
-    const double cov = matern_r<NU>(r, P.sigma2) + (a == b ? P.tau2 : 0.0);
+// Entry (a, b) of the augmented block given the covariance value `cov` of the
+// two points: nugget on the diagonal, the observation row k+1, identity padding.
+__device__ __forceinline__ double block_value(int a, int b, int k, double cov, const double *__restrict__ Z,
+                                              const Params &P) {
     const int hi = a > b ? a : b, lo = a > b ? b : a;
-    double v = cov;
+    double v = cov + (a == b ? P.tau2 : 0.0);
     if (hi == k + 1) v = (lo == k + 1) ? 1.0 : Z[lo];
     if (hi > k + 1) v = (a == b) ? 1.0 : 0.0;
     return v;
@@ -275,16 +283,34 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     }
     __syncthreads();
 
-    // covariance generation straight into the register tiles
+    // covariance generation straight into the register tiles; with the
+    // gradient, dC/dbeta of the strictly lower part (rows <= k) is kept in
+    // dtile from the same exponential
+    constexpr bool KEEP_D = GRAD && VECCHIA_KEEP_DBETA;
     dvec4 tile[NTW];
+    dvec4 dtile[KEEP_D ? NTW : 1];
+    const double s2b = P.sigma2 * P.inv_beta;
 #pragma unroll
     for (int s = 0; s < NTW; ++s) {
         if (SR(s) >= 0) {
             const int a = 16 * SR(s) + j;
+            const double xa = XY[2 * a], ya = XY[2 * a + 1];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tile[s][r] = block_entry<NU>(a, 16 * SC(s) + 4 * r + g, k, XY, Z, P);
+            for (int r = 0; r < 4; ++r) {
+                const int b = 16 * SC(s) + 4 * r + g;
+                const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
+                double cov, db;
+                if constexpr (KEEP_D) {
+                    matern_and_dbeta_r<NU>(rb, P.sigma2, s2b, cov, db);
+                    dtile[s][r] = (a > b && a <= k) ? db : 0.0;
+                } else {
+                    cov = matern_r<NU>(rb, P.sigma2);
+                }
+                tile[s][r] = block_value(a, b, k, cov, Z, P);
+            }
         } else {
             tile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (KEEP_D) dtile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
         }
     }
 
@@ -396,18 +422,26 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         double ub = 0.0;
         for (int t = tid; t <= k; t += NT) ub += U[t] * BH[t];
         double gb = 0.0;
-        const double s2b = P.sigma2 * P.inv_beta;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SR(s) >= 0) {
                 const int a = 16 * SR(s) + j;
-                const double ua = U[a], ba = BH[a], xa = XY[2 * a], ya = XY[2 * a + 1];
+                const double ua = U[a], ba = BH[a];
+                if constexpr (KEEP_D) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int b = 16 * SC(s) + 4 * r + g;
-                    if (a > b && a <= k) {
-                        const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
-                        gb += matern_dbeta_r<NU>(rb, s2b) * (ua * BH[b] + U[b] * ba);
+                    for (int r = 0; r < 4; ++r) {
+                        const int b = 16 * SC(s) + 4 * r + g;
+                        gb = fma(dtile[s][r], ua * BH[b] + U[b] * ba, gb);
+                    }
+                } else {
+                    const double xa = XY[2 * a], ya = XY[2 * a + 1];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int b = 16 * SC(s) + 4 * r + g;
+                        if (a > b && a <= k) {
+                            const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
+                            gb += matern_dbeta_r<NU>(rb, s2b) * (ua * BH[b] + U[b] * ba);
+                        }
                     }
                 }
             }

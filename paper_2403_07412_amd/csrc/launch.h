@@ -34,7 +34,8 @@ struct LdsImpl {
 template <int T, int W, int NU, bool GRAD>
 struct TileImpl {
     static constexpr int NT = W * kWave;
-    static constexpr int WPE = VECCHIA_WPE_OVERRIDE > 0 ? VECCHIA_WPE_OVERRIDE : tile_waves_per_simd(T, W);
+    static constexpr int WPE =
+        VECCHIA_WPE_OVERRIDE > 0 ? VECCHIA_WPE_OVERRIDE : tile_waves_per_simd(T, W, GRAD && VECCHIA_KEEP_DBETA);
     static size_t smem(int) { return TileLds<T>::BYTES; }
     static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int32_t m,
                                   const Params &P, double *sm) {
@@ -42,20 +43,79 @@ struct TileImpl {
     }
 };
 
-// One workgroup per listed point t (point i = idx[t], or t when idx is NULL).
-// Writes l_i to ell[t * ell_stride] and the gradient to g[t * g_stride + 0..2]
-// (NaN on failure), and reports failure through flags[t] (when given) or as
-// atomicMin(status, t + 1) (when given).
+// A field of a batched evaluation, as the device sees it.
+struct FieldDev {
+    const double *locs;   // [n][2]
+    const double *z;      // [n]
+    const int32_t *nbr;   // [n][m]
+    int64_t n;
+    int32_t m;
+    int32_t eval0;        // evaluation index of (this field, theta 0); evaluation e = field * ntheta + theta
+    int64_t vals0;        // row of (this field, theta 0, point 0) in the per-point value array
+};
+
+// Arguments of one conditional-kernel launch (passed by value).
+//   single mode (fields == NULL): item t is point idx[t] (or t) of one field;
+//     results go to ell[t * ell_stride], g[t * g_stride + 0..2], flags[t] or status;
+//   batched mode: the items of a tile class, t in [0, item0[nfc]); item t lies
+//     in class field c (item0[c] <= t < item0[c+1]) = fields[fidx[c]], with
+//     theta index p and point i from t - item0[c] = p n + i; results go to row
+//     vals0 + p n + i of ell / g / flags, parameters to theta + 3 (eval0 + p).
+struct KernelArgs {
+    const double *locs, *z;
+    const int32_t *nbr;
+    int64_t n;
+    int32_t m;
+    const double *theta;
+    const int64_t *idx;
+    const FieldDev *fields;
+    const int32_t *fidx;
+    const int64_t *item0;
+    int32_t nfc;
+    double *ell;
+    int64_t ell_stride;
+    double *g;
+    int64_t g_stride;
+    int32_t *flags;
+    unsigned long long *status;
+    int64_t t0;
+};
+
+// One workgroup per item (a point of one evaluation).  Failure is reported
+// through flags[row] (when given) or as atomicMin(status, t + 1) (when given);
+// failed rows hold NaN.
 template <class Impl>
 __global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(Impl::WPE)))
-    cond_kernel(const double *__restrict__ locs, const double *__restrict__ z, const int32_t *__restrict__ nbr,
-                int64_t n, int32_t m, const double *__restrict__ theta, const int64_t *__restrict__ idx,
-                int64_t t0, double *__restrict__ ell, int64_t ell_stride, double *__restrict__ g,
-                int64_t g_stride, int32_t *__restrict__ flags, unsigned long long *__restrict__ status) {
+    cond_kernel(const KernelArgs a) {
     extern __shared__ double smem[];
+    const int64_t t = a.t0 + blockIdx.x;
+    const double *locs = a.locs, *z = a.z, *theta = a.theta;
+    const int32_t *nbr = a.nbr;
+    int64_t n = a.n, i, row;
+    int32_t m = a.m;
+    if (a.fields) {
+        int lo = 0, hi = a.nfc;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.item0[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const FieldDev &F = a.fields[a.fidx[lo]];
+        locs = F.locs;
+        z = F.z;
+        nbr = F.nbr;
+        n = F.n;
+        m = F.m;
+        const int64_t r = t - a.item0[lo];
+        const int64_t p = r / n;
+        i = r - p * n;
+        theta = a.theta + 3 * ((int64_t)F.eval0 + p);
+        row = F.vals0 + r;
+    } else {
+        i = a.idx ? a.idx[t] : t;
+        row = t;
+    }
     const Params P = load_params(theta);
-    const int64_t t = t0 + blockIdx.x;
-    const int64_t i = idx ? idx[t] : t;
     CondOut o;
     bool bad = true;
     if (P.valid && i >= 0 && i < n) {  // uniform over the workgroup
@@ -64,14 +124,14 @@ __global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(I
     }
     if (bad) o.ell = o.g0 = o.g1 = o.g2 = __builtin_nan("");
     if (threadIdx.x == 0) {
-        ell[t * ell_stride] = o.ell;
-        if (g) {
-            g[t * g_stride + 0] = o.g0;
-            g[t * g_stride + 1] = o.g1;
-            g[t * g_stride + 2] = o.g2;
+        a.ell[row * a.ell_stride] = o.ell;
+        if (a.g) {
+            a.g[row * a.g_stride + 0] = o.g0;
+            a.g[row * a.g_stride + 1] = o.g1;
+            a.g[row * a.g_stride + 2] = o.g2;
         }
-        if (flags) flags[t] = bad ? 1 : 0;
-        if (status && bad && P.valid) atomicMin(status, (unsigned long long)(t + 1));
+        if (a.flags) a.flags[row] = bad ? 1 : 0;
+        if (a.status && bad && P.valid) atomicMin(a.status, (unsigned long long)(t + 1));
     }
 }
 
@@ -80,34 +140,26 @@ hipError_t allow_smem(K kernel, size_t bytes) {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Arguments of one conditional-kernel launch.
+// A launch request: kernel arguments plus the item range [t_begin, t_end)
+// and the largest m among the items (sizes the LDS of the unblocked kernel).
 struct EvalArgs {
-    const double *locs, *z;
-    const int32_t *nbr;
-    int64_t n;
-    int32_t m;
-    const double *theta;
-    const int64_t *idx;
-    int64_t nidx;
-    double *ell;
-    int64_t ell_stride;
-    double *g;
-    int64_t g_stride;
-    int32_t *flags;
-    unsigned long long *status;
+    KernelArgs k;
+    int64_t t_begin, t_end;
+    int32_t m_max;
 };
 
 template <class Impl>
 int launch_cond_impl(const EvalArgs &a, hipStream_t s) {
-    if (a.nidx == 0) return VECCHIA_OK;
-    const size_t smem = Impl::smem(a.m);
+    if (a.t_end <= a.t_begin) return VECCHIA_OK;
+    const size_t smem = Impl::smem(a.m_max);
     auto kern = cond_kernel<Impl>;
     if (allow_smem(kern, smem) != hipSuccess) return VECCHIA_EHIP;
-    constexpr int64_t kMaxGrid = (int64_t)1 << 22;  // blocks per launch; larger lists take several launches
-    for (int64_t t0 = 0; t0 < a.nidx; t0 += kMaxGrid) {
-        const int64_t grid = std::min<int64_t>(a.nidx - t0, kMaxGrid);
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(Impl::NT), smem, s, a.locs, a.z, a.nbr, a.n, a.m, a.theta,
-                           a.idx, t0, a.ell, a.ell_stride, a.g, a.g_stride, a.flags, a.status);
+    constexpr int64_t kMaxGrid = (int64_t)1 << 22;  // workgroups per launch; longer ranges take several launches
+    for (int64_t t0 = a.t_begin; t0 < a.t_end; t0 += kMaxGrid) {
+        const int64_t grid = std::min<int64_t>(a.t_end - t0, kMaxGrid);
+        KernelArgs k = a.k;
+        k.t0 = t0;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(Impl::NT), smem, s, k);
     }
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
@@ -173,7 +225,7 @@ int launch_tile_w(int T, const EvalArgs &a, hipStream_t s) {
 
 template <int NU, bool GRAD>
 int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
-    const int T = tile_rows(a.m);
+    const int T = tile_rows(a.m_max);
     switch (variant) {
         case V_UNBLOCKED:
             return launch_cond_impl<LdsImpl<NU, GRAD>>(a, s);
@@ -184,6 +236,14 @@ int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
         default: return VECCHIA_EUNSUPPORTED;
     }
 }
+
+// Defined in vecchia.hip: smoothness code (0, 1, 2 for nu = 0.5, 1.5, 2.5;
+// -1 otherwise), the variant a launch uses for (m, gradient), the host-side
+// variant table, and the launcher for any smoothness.
+int nu_code(double nu);
+int resolve_variant(int m, bool grad, int requested);
+extern int g_variant[2][VECCHIA_MAX_M + 1];
+int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s);
 
 // Defined in kernels_nu05.hip, kernels_nu15.hip and kernels_nu25.hip.
 int launch_nu05(bool grad, int variant, const EvalArgs &a, hipStream_t s);

@@ -19,19 +19,42 @@
 
 #include "vecchia.h"
 #include "launch.h"
+#include "reduce.h"
 
 using namespace vecchia;
 
+namespace vecchia {
+
+// ---------------------------------------------------------------- dispatch
+// host-side variant table, indexed by [with_grad][m]; 0 = default
+int g_variant[2][VECCHIA_MAX_M + 1] = {};
+
+int resolve_variant(int m, bool grad, int requested) {
+    int v = requested != V_AUTO ? requested : g_variant[grad ? 1 : 0][m];
+    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m);
+    return v;
+}
+
+int nu_code(double nu) {
+    if (nu == 0.5) return 0;
+    if (nu == 1.5) return 1;
+    if (nu == 2.5) return 2;
+    return -1;
+}
+
+int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s) {
+    switch (nuc) {
+        case 0: return launch_nu05(grad, variant, a, s);
+        case 1: return launch_nu15(grad, variant, a, s);
+        default: return launch_nu25(grad, variant, a, s);
+    }
+}
+
+}  // namespace vecchia
+
 namespace {
 
-constexpr int kFinalizeThreads = 256;
-
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-
-constexpr int kReduceThreads = 256;
-constexpr int64_t kPointsPerReduceBlock = (int64_t)kChunk * kReduceThreads;
-
-int64_t num_reduce_blocks(int64_t n) { return (n + kPointsPerReduceBlock - 1) / kPointsPerReduceBlock; }
 
 // Workspace layout: per-point values [n][4] double, per-point flags [n] int32,
 // then per-reduce-block partials [nb][4] double-double and first failures [nb] int64.
@@ -59,48 +82,11 @@ WsLayout ws_layout(void *ws, int64_t n) {
     return L;
 }
 
-// Level 1 of the fixed-order sum: thread c of the grid adds points
-// [c kChunk, (c+1) kChunk) in ascending order; each workgroup combines its
-// threads in a fixed tree (double-double) into partial[block].
 __global__ void __launch_bounds__(kReduceThreads) reduce_kernel(const double *__restrict__ vals,
                                                                 const int32_t *__restrict__ flags, int64_t n,
                                                                 double *__restrict__ partial,
                                                                 int64_t *__restrict__ pfail) {
-    __shared__ DD sh[4][kReduceThreads];
-    __shared__ int64_t shf[kReduceThreads];
-    const int t = threadIdx.x;
-    const int64_t i0 = ((int64_t)blockIdx.x * kReduceThreads + t) * kChunk;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t f = kNoFailure;
-    for (int64_t i = i0; i < i0 + kChunk && i < n; ++i) {
-        a0 += vals[4 * i + 0];
-        a1 += vals[4 * i + 1];
-        a2 += vals[4 * i + 2];
-        a3 += vals[4 * i + 3];
-        if (flags[i] && f == kNoFailure) f = i + 1;
-    }
-    sh[0][t] = DD{a0, 0.0};
-    sh[1][t] = DD{a1, 0.0};
-    sh[2][t] = DD{a2, 0.0};
-    sh[3][t] = DD{a3, 0.0};
-    shf[t] = f;
-    __syncthreads();
-    for (int s = kReduceThreads / 2; s > 0; s >>= 1) {
-        if (t < s) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sh[q][t] = dd_add(sh[q][t], sh[q][t + s]);
-            shf[t] = min(shf[t], shf[t + s]);
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            partial[8 * blockIdx.x + 2 * q] = sh[q][0].hi;
-            partial[8 * blockIdx.x + 2 * q + 1] = sh[q][0].lo;
-        }
-        pfail[blockIdx.x] = shf[0];
-    }
+    reduce_segment_block(vals, flags, n, blockIdx.x, partial + 8 * (int64_t)blockIdx.x, pfail + blockIdx.x);
 }
 
 __global__ void status_init_kernel(unsigned long long *status) {
@@ -117,8 +103,6 @@ __global__ void status_fix_kernel(unsigned long long *status, const double *__re
     }
 }
 
-// Level 2 of the fixed-order sum: the reduce-block partials (double-double)
-// in a fixed order; writes l, the gradient and the status.
 __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double *__restrict__ partial,
                                                                     const int64_t *__restrict__ pfail,
                                                                     int64_t nblocks,
@@ -126,70 +110,7 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double
                                                                     double *__restrict__ out,
                                                                     double *__restrict__ grad,
                                                                     int64_t *__restrict__ status) {
-    __shared__ DD sh[4][kFinalizeThreads];
-    __shared__ int64_t shf[kFinalizeThreads];
-    const int t = threadIdx.x;
-    const Params P = load_params(theta);
-    DD a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    int64_t f = kNoFailure;
-    if (P.valid) {
-        for (int64_t c = t; c < nblocks; c += kFinalizeThreads) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = dd_add(a[q], DD{partial[8 * c + 2 * q], partial[8 * c + 2 * q + 1]});
-            f = min(f, pfail[c]);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sh[q][t] = a[q];
-    shf[t] = f;
-    __syncthreads();
-    for (int s = kFinalizeThreads / 2; s > 0; s >>= 1) {
-        if (t < s) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sh[q][t] = dd_add(sh[q][t], sh[q][t + s]);
-            shf[t] = min(shf[t], shf[t + s]);
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        const double nan = __builtin_nan("");
-        int64_t st;
-        if (!P.valid) st = VECCHIA_STATUS_THETA;
-        else st = (shf[0] == kNoFailure) ? 0 : shf[0];
-        const bool ok = (st == 0);
-        out[0] = ok ? sh[0][0].hi + sh[0][0].lo : nan;
-        if (grad) {
-            grad[0] = ok ? sh[1][0].hi + sh[1][0].lo : nan;
-            grad[1] = ok ? sh[2][0].hi + sh[2][0].lo : nan;
-            grad[2] = ok ? sh[3][0].hi + sh[3][0].lo : nan;
-        }
-        status[0] = st;
-    }
-}
-
-// ---------------------------------------------------------------- dispatch
-// host-side variant table, indexed by [with_grad][m]; 0 = default
-int g_variant[2][VECCHIA_MAX_M + 1] = {};
-
-int resolve_variant(int m, bool grad, int requested) {
-    int v = requested != V_AUTO ? requested : g_variant[grad ? 1 : 0][m];
-    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m);
-    return v;
-}
-
-int nu_code(double nu) {
-    if (nu == 0.5) return 0;
-    if (nu == 1.5) return 1;
-    if (nu == 2.5) return 2;
-    return -1;
-}
-
-int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s) {
-    switch (nuc) {
-        case 0: return launch_nu05(grad, variant, a, s);
-        case 1: return launch_nu15(grad, variant, a, s);
-        default: return launch_nu25(grad, variant, a, s);
-    }
+    finalize_segment(partial, pfail, nblocks, theta, out, grad, status);
 }
 
 int check_common(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
@@ -213,12 +134,22 @@ int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, 
     WsLayout L = ws_layout(ws, n);
     if (!ws || ws_bytes < L.bytes) return VECCHIA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    EvalArgs a{locs, z, nbr, n, m, theta, nullptr, n, L.vals, 4, with_grad ? L.vals + 1 : nullptr, 4, L.flags,
-               nullptr};
-    if (!with_grad) {
-        // the gradient slots of vals stay unwritten; the reduction still reads them
-        if (n > 0 && hipMemsetAsync(L.vals, 0, (size_t)n * 4 * sizeof(double), s) != hipSuccess) return VECCHIA_EHIP;
-    }
+    // the gradient columns are always written (zeros for a value-only evaluation)
+    EvalArgs a{};
+    a.k.locs = locs;
+    a.k.z = z;
+    a.k.nbr = nbr;
+    a.k.n = n;
+    a.k.m = m;
+    a.k.theta = theta;
+    a.k.ell = L.vals;
+    a.k.ell_stride = 4;
+    a.k.g = L.vals + 1;
+    a.k.g_stride = 4;
+    a.k.flags = L.flags;
+    a.t_begin = 0;
+    a.t_end = n;
+    a.m_max = m;
     rc = launch_any(nu_code(nu), with_grad, resolve_variant(m, with_grad, variant), a, s);
     if (rc != VECCHIA_OK) return rc;
     const int64_t nb = num_reduce_blocks(n);
@@ -239,7 +170,22 @@ int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n
     hipStream_t s = (hipStream_t)stream;
     unsigned long long *st = (unsigned long long *)status;
     const bool g = gterms != nullptr;
-    EvalArgs a{locs, z, nbr, n, m, theta, idx, nidx, terms, 1, gterms, 3, nullptr, st};
+    EvalArgs a{};
+    a.k.locs = locs;
+    a.k.z = z;
+    a.k.nbr = nbr;
+    a.k.n = n;
+    a.k.m = m;
+    a.k.theta = theta;
+    a.k.idx = idx;
+    a.k.ell = terms;
+    a.k.ell_stride = 1;
+    a.k.g = gterms;
+    a.k.g_stride = 3;
+    a.k.status = st;
+    a.t_begin = 0;
+    a.t_end = nidx;
+    a.m_max = m;
     hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, s, st);
     rc = launch_any(nu_code(nu), g, resolve_variant(m, g, variant), a, s);
     if (rc != VECCHIA_OK) return rc;

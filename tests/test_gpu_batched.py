@@ -1,0 +1,144 @@
+"""Batched evaluation (many fields, many parameter vectors), its graph capture and the autotuner.
+
+The batched form must equal single calls with the same kernel variant bit for
+bit (same per-point kernels, same fixed summation order), match the oracle to
+the parity tolerances, and give the eager results on every graph replay.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from util import assert_grad_close, assert_total_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2403_07412_amd as v
+    v.library()
+    return v
+
+
+def make_fields(rng, specs, nu):
+    import torch
+    out = []
+    for n, m in specs:
+        f = wl.small_field(rng, n, m, nu, (1.0, 0.1, 0.0))
+        dev = torch.device("cuda:0")
+        nbr = torch.from_numpy(f.nbr).to(dev) if m > 0 else torch.empty((n, 0), dtype=torch.int32, device=dev)
+        out.append((f, (torch.from_numpy(f.locs).to(dev), torch.from_numpy(f.z).to(dev), nbr, m)))
+    return out
+
+
+def random_thetas(rng, nf, ntheta):
+    th = np.stack([rng.uniform(0.5, 2.0, (nf, ntheta)), rng.uniform(0.03, 0.2, (nf, ntheta)),
+                   rng.uniform(1e-5, 1e-3, (nf, ntheta))], axis=-1)
+    return th
+
+
+SPECS = [(700, 10), (1500, 30), (0, 20), (900, 62), (1, 5), (400, 120), (333, 150), (2000, 47)]
+
+
+@pytest.mark.parametrize("with_grad", [True, False])
+def test_batched_equals_single_calls_bitwise_and_oracle(v, with_grad):
+    import torch
+    rng = np.random.default_rng(77)
+    nu = 1.5
+    fields = make_fields(rng, SPECS, nu)
+    ntheta = 3
+    th = random_thetas(rng, len(SPECS), ntheta)
+    thetas = torch.from_numpy(th).cuda()
+    plan = v.BatchedPlan([f[1] for f in fields], ntheta, nu, with_grad)
+    print("classes", plan.classes(), flush=True)
+    out, grad, status = plan(thetas)
+    torch.cuda.synchronize()
+    assert (status == 0).all()
+    class_variant = {T: var for T, var, _, _ in plan.classes()}
+    for fi, (f, (locs, z, nbr, m)) in enumerate(fields):
+        for q in range(ntheta):
+            if f.n == 0:
+                assert out[fi, q].item() == 0.0
+                continue
+            variant = class_variant[(m + 2 + 15) // 16]
+            o1, g1, s1 = v.vecchia_loglik_variant(locs, z, nbr if m > 0 else None, m, nu, thetas[fi, q].contiguous(),
+                                                  variant, with_grad=with_grad)
+            torch.cuda.synchronize()
+            assert int(s1.item()) == 0
+            assert torch.equal(o1[0], out[fi, q]), (fi, q)
+            if with_grad:
+                assert torch.equal(g1, grad[fi, q])
+            ell, gt = oracle.terms(f.locs, f.z, f.nbr, m, nu, th[fi, q], with_grad=True)
+            assert_total_close(out[fi, q].item(), oracle.compensated_sum(ell), 1e-10, f"field {fi} theta {q}")
+            if with_grad:
+                assert_grad_close(grad[fi, q].cpu().numpy(), [oracle.compensated_sum(gt[:, p]) for p in range(3)],
+                                  np.abs(gt).sum(0), 1e-9, f"field {fi} theta {q}")
+    plan.close()
+
+
+def test_graph_replays_match_eager(v):
+    import torch
+    rng = np.random.default_rng(78)
+    nu = 0.5
+    fields = make_fields(rng, [(1200, 30), (800, 90), (500, 14)], nu)
+    ntheta = 4
+    plan = v.BatchedPlan([f[1] for f in fields], ntheta, nu, True)
+    thetas = torch.from_numpy(random_thetas(rng, 3, ntheta)).cuda()
+    out, grad, status = plan.outputs()
+    graph = plan.capture(thetas, out, grad, status)
+    for rep in range(4):
+        new = torch.from_numpy(random_thetas(rng, 3, ntheta)).cuda()
+        thetas.copy_(new)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        got = (out.clone(), grad.clone(), status.clone())
+        # eager work in between replays
+        e_out, e_grad, e_status = plan(thetas)
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], e_out) and torch.equal(got[1], e_grad) and torch.equal(got[2], e_status), rep
+        assert (e_status == 0).all()
+        del junk
+    graph.close()
+    plan.close()
+
+
+def test_batched_reports_failure_per_evaluation(v):
+    import torch
+    rng = np.random.default_rng(79)
+    nu = 0.5
+    fields = make_fields(rng, [(300, 10), (300, 10)], nu)
+    # second field: points 0 and 1 coincide -> with sigma2 = 1, tau2 = 0 point 1 fails exactly
+    f, (locs, z, nbr, m) = fields[1]
+    f.locs[1] = f.locs[0]
+    f.nbr = wl.nearest_previous_neighbours(f.locs, 10)
+    locs.copy_(torch.from_numpy(f.locs))
+    nbr.copy_(torch.from_numpy(f.nbr))
+    plan = v.BatchedPlan([fl[1] for fl in fields], 2, nu, True)
+    th = np.array([[[1.0, 0.1, 0.0], [1.0, 0.1, 1e-2]], [[1.0, 0.1, 0.0], [-1.0, 0.1, 0.0]]])
+    out, grad, status = plan(torch.from_numpy(th).cuda())
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[0, 0] == 0 and st[0, 1] == 0
+    assert st[1, 0] == 2          # point 1 of field 1
+    assert st[1, 1] == -1         # invalid theta
+    assert np.isnan(out[1, 0].item()) and np.isnan(out[1, 1].item())
+    assert np.isfinite(out[0].cpu().numpy()).all()
+    plan.close()
+
+
+def test_autotune_sets_a_feasible_variant(v):
+    import torch
+    rng = np.random.default_rng(80)
+    f, (locs, z, nbr, m) = make_fields(rng, [(6000, 60)], 1.5)[0]
+    theta = torch.tensor([1.0, 0.05, 1e-5], dtype=torch.float64, device="cuda")
+    before = v.vecchia_get_variant(60, True)
+    best, times = v.vecchia_autotune(locs, z, nbr, 60, 1.5, theta, True, sample=3000, reps=2)
+    print("autotune m=60", best, times, flush=True)
+    assert v.vecchia_variant_feasible(60, best)
+    assert v.vecchia_get_variant(60, True) == best
+    assert all(t > 0 for t in times.values())
+    assert min(times, key=times.get) == {val: k for k, val in v.VARIANTS.items()}[best]
+    v.vecchia_set_variant(60, True, before)
