@@ -434,3 +434,30 @@ def vecchia_autotune(locs, z, nbr, m: int, nu: float, theta, with_grad: bool, sa
     _check(rc, "vecchia_autotune")
     names = {v: k for k, v in VARIANTS.items()}
     return best.value, {names[v]: us[v] for v in range(1, 6) if us[v] >= 0}
+
+
+def variant_table():
+    """The variant each (m, with_grad) uses now: {"grad": [...161], "value": [...161]}."""
+    return {"value": [vecchia_get_variant(m, False) for m in range(VECCHIA_MAX_M + 1)],
+            "grad": [vecchia_get_variant(m, True) for m in range(VECCHIA_MAX_M + 1)]}
+
+
+def save_variant_table(path: str) -> None:
+    """Writes the current variant table (e.g. after autotuning) as JSON."""
+    import json
+
+    with open(path, "w") as fh:
+        json.dump({"format": "vecchia-variant-table-1", **variant_table()}, fh)
+
+
+def load_variant_table(path: str) -> None:
+    """Loads a table written by save_variant_table into the library (infeasible entries are rejected)."""
+    import json
+
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("format") != "vecchia-variant-table-1":
+        raise ValueError(f"{path}: not a variant table")
+    for key, grad in (("value", False), ("grad", True)):
+        for m, var in enumerate(data[key]):
+            vecchia_set_variant(m, grad, int(var))

@@ -63,6 +63,13 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d)
     return wps;
 }
 
+// Whether the gradient keeps the beta-derivative tiles in registers (one
+// exponential per entry) or recomputes them after the solves: kept only when
+// the extra registers cost no occupancy.
+__host__ __device__ constexpr bool keep_dbeta(int T, int W) {
+    return VECCHIA_KEEP_DBETA && tile_waves_per_simd(T, W, true) >= tile_waves_per_simd(T, W, false);
+}
+
 // LDS layout of the tiled kernel, in doubles.
 template <int T>
 struct TileLds {
@@ -113,14 +120,42 @@ __device__ __forceinline__ double bcast_row(double v) {
     return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xF, 0xF, false);
 }
 
-// acc += v(lane SRC of this lane's row) * w, one fused 64-bit DPP FMA.  The
-// leading s_nop gives the two wait states a DPP source needs after a VALU
-// write (the compiler does not track hazards inside inline assembly).
-template <int SRC>
+// acc += v(lane SRC of this lane's row) * w, one fused 64-bit DPP FMA.  With
+// NOP, two wait states precede it: a DPP source written by the instruction
+// just before needs them, and the compiler does not look inside inline
+// assembly for that hazard.
+template <int SRC, bool NOP>
 __device__ __forceinline__ void fma_bcast_row(double &acc, double v, double w) {
-    asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-                 : "+v"(acc)
-                 : "v"(v), "v"(w), "i"(SRC));
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(v), "v"(w), "i"(SRC));
+    else
+        asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(v), "v"(w), "i"(SRC));
+}
+
+// acc += acc(lane SRC of this lane's row) * w: the accumulator is also the
+// broadcast source (one register, no copy).
+template <int SRC, bool NOP>
+__device__ __forceinline__ void fma_bcast_row_self(double &acc, double w) {
+    if constexpr (NOP)
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(w), "i"(SRC));
+    else
+        asm volatile("v_fmac_f64_dpp %0, %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+                     : "+v"(acc)
+                     : "v"(w), "i"(SRC));
+}
+
+// 32-bit DPP move of both halves of a double (any DPP control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
 // compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1
@@ -142,11 +177,13 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
 }
 
 __device__ __forceinline__ double sum16(double v) {
-    // sum over the 16 lanes of a row; every lane of the row gets the result
-    v += __shfl_xor(v, 1, kWave);
-    v += __shfl_xor(v, 2, kWave);
-    v += __shfl_xor(v, 4, kWave);
-    v += __shfl_xor(v, 8, kWave);
+    // sum over the 16 lanes of a row with DPP: pairs, quads, half rows, rows.
+    // Every lane adds the same partial sums (a + b == b + a), so all 16 lanes
+    // hold bitwise the same total.
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
     return v;
 }
 
@@ -178,6 +215,9 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
     const int g = l / 16, j = l % 16;
     double *S = smem + Ls::DIAG;  // the caller stored the tile here, row-major with stride 17
+    // this wave is the critical path of the workgroup: let it win instruction
+    // issue over the other waves sharing its SIMD while it factors
+    __builtin_amdgcn_s_setprio(3);
     wave_lds_sync();
     double R[16];
 #pragma unroll
@@ -188,12 +228,15 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     const int base = 16 * t;
     const int jk = k - base;      // local index of row k (point i) if it lies in this tile
     const int jy = k + 1 - base;  // local index of row k+1 (observations) if it lies in this tile
-    // Linv is built row by row alongside the factor: lane (g, j) keeps
-    // Linv[j][4r + g] (r = 0..3) in Wr, i.e. Linv in T-layout.
+    // Linv is built row by row alongside the factor.  Lane (g, j) keeps
+    // W_j[4r + g] (r = 0..3), row j of the unit-scaled inverse: once column q
+    // is known, W_j -= (L[j][q] / L[q][q]) W_q for the rows j below q, with
+    // W_q broadcast from lane q; finally Linv[j][.] = W_j / L[j][j].  The
+    // result is Linv in T-layout.
     double Wr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] = (j == 4 * r + g) ? 1.0 : 0.0;
-    double dk = 0.0;
+    double dk = 0.0, myinv = 1.0;
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
@@ -204,20 +247,24 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
             d = piv * inv;
         }
         if (q == jk) dk = d;
-        R[q] = (j > q) ? R[q] * inv : ((j == q) ? d : 0.0);  // column q of L
-        // row q of Linv is final: Linv[q][.] = W_q / L_qq; eliminate it from the rows below
+        const double lq = R[q] * inv;                      // L[j][q] for rows below q
+        myinv = (j == q) ? inv : myinv;
+        const double nlq_inv = (j > q) ? -(lq * inv) : 0.0;  // -L[j][q] / L[q][q]
+        R[q] = (j > q) ? lq : ((j == q) ? d : 0.0);        // column q of L
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double bq = bcast_row<q>(Wr[r]) * inv;
-            Wr[r] = (j == q) ? bq : ((j > q) ? fma(-R[q], bq, Wr[r]) : Wr[r]);
+            if (r == 0) fma_bcast_row_self<q, true>(Wr[r], nlq_inv);
+            else fma_bcast_row_self<q, false>(Wr[r], nlq_inv);
         }
         // trailing update of the tile: R[c] -= L[j][q] L[c][q], L[c][q] broadcast from lane c
         const double nRq = -R[q];
         static_for<q + 1, 16>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            fma_bcast_row<c>(R[c], R[q], nRq);
+            fma_bcast_row<c, c == q + 1>(R[c], R[q], nRq);
         });
     });
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wr[r] *= myinv;
     if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = dk;
     if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
@@ -227,6 +274,7 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     double *Li = smem + Ls::LINV + t * 256 + l * 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) Li[r] = Wr[r];
+    __builtin_amdgcn_s_setprio(0);
     return bad;
 }
 
@@ -286,7 +334,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     // covariance generation straight into the register tiles; with the
     // gradient, dC/dbeta of the strictly lower part (rows <= k) is kept in
     // dtile from the same exponential
-    constexpr bool KEEP_D = GRAD && VECCHIA_KEEP_DBETA;
+    constexpr bool KEEP_D = GRAD && keep_dbeta(T, W);
     dvec4 tile[NTW];
     dvec4 dtile[KEEP_D ? NTW : 1];
     const double s2b = P.sigma2 * P.inv_beta;
@@ -318,8 +366,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
         // 1. diagonal tile t (already fully updated by its owner)
-        const int own_d = tile_index(T, t, t) % W;
-        if (w == own_d) {
+        if (w == tile_index(T, t, t) % W) {
             const int sd = tile_index(T, t, t) / W;
 #pragma unroll
             for (int s = 0; s < NTW; ++s) {
@@ -388,6 +435,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
             if (w == tile_index(T, t, t) % W) {
+                __builtin_amdgcn_s_setprio(3);
                 const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
                 const double q1 = Q1[16 * t + j], q2 = Q2[16 * t + j];
 #pragma unroll
@@ -399,6 +447,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                         BH[16 * t + 4 * r + g] = p2;
                     }
                 }
+                __builtin_amdgcn_s_setprio(0);
             }
             __syncthreads();
 #pragma unroll

@@ -35,7 +35,7 @@ template <int T, int W, int NU, bool GRAD>
 struct TileImpl {
     static constexpr int NT = W * kWave;
     static constexpr int WPE =
-        VECCHIA_WPE_OVERRIDE > 0 ? VECCHIA_WPE_OVERRIDE : tile_waves_per_simd(T, W, GRAD && VECCHIA_KEEP_DBETA);
+        VECCHIA_WPE_OVERRIDE > 0 ? VECCHIA_WPE_OVERRIDE : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W));
     static size_t smem(int) { return TileLds<T>::BYTES; }
     static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int32_t m,
                                   const Params &P, double *sm) {

@@ -63,3 +63,21 @@ def test_argument_errors_are_synchronous(lib):
     # terms: idx NULL needs nidx == n
     assert lib.vecchia_loglik_terms(dummy, dummy, dummy, 100, 10, 0.5, dummy, None, 5, dummy, None, dummy,
                                     None) == 1
+
+
+def test_variant_table_roundtrip_on_host(tmp_path, lib):
+    import paper_2403_07412_amd as v
+    before = v.variant_table()
+    assert len(before["grad"]) == v.VECCHIA_MAX_M + 1
+    for m in range(v.VECCHIA_MAX_M + 1):
+        assert v.vecchia_variant_feasible(m, before["grad"][m])
+    v.vecchia_set_variant(60, True, "unblocked")
+    path = tmp_path / "table.json"
+    v.save_variant_table(str(path))
+    v.vecchia_set_variant(60, True, "auto")
+    assert v.vecchia_get_variant(60, True) == before["grad"][60]
+    v.load_variant_table(str(path))
+    assert v.vecchia_get_variant(60, True) == 1
+    v.vecchia_set_variant(60, True, "auto")
+    with pytest.raises(v.VecchiaError):
+        v.vecchia_set_variant(150, True, "tile_w1")
