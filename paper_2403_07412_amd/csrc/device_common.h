@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "exp_table.h"
+
 namespace vecchia {
 
 constexpr int kWave = 64;                     // CDNA wavefront width
@@ -72,6 +74,68 @@ __device__ __forceinline__ double sqrt_dist(double s) {
     const double d = fma(-g, g, s);
     g = fma(d, h, g);
     return (s > 1e-290) ? g : ((s >= 0.0) ? 0.0 : s);
+}
+
+// e^{-r} for r >= 0 by Tang's table-driven method: -r = (64 k + j) ln2/64 + f
+// with |f| <= ln2/128, so e^{-r} = 2^k 2^{j/64} e^f.  `tab` holds 2^{j/64}
+// as hi + lo pairs (kExp2Frac64, staged in LDS by the caller); q = e^f - 1 by
+// its Taylor polynomial of degree 6 (truncation below 3e-20), and the result
+// hi + (lo + hi q) rounds once at the end, so the error stays just above half
+// an ulp.  ln2/64 is split into a 36-bit head (n ln2/64 exact for |n| < 2^17)
+// and a tail.  Arguments beyond 746 give 0; a NaN argument gives 0 as well,
+// so callers validate their inputs instead.
+__device__ __forceinline__ double exp_neg_tab(double r, const double *tab) {
+    const double x = fmax(-r, -746.0);
+    const double nf = __builtin_rint(x * 0x1.71547652b82fep+6);  // 64 / ln2
+    const int n = (int)nf;
+    double f = fma(nf, -0x1.62e42fefa0000p-7, x);  // head of ln2/64
+    f = fma(nf, -0x1.cf79abc9e3b3ap-46, f);        // tail of ln2/64
+    double q = fma(f, 1.0 / 720.0, 1.0 / 120.0);
+    q = fma(q, f, 1.0 / 24.0);
+    q = fma(q, f, 1.0 / 6.0);
+    q = fma(q, f, 0.5);
+    q = fma(q, f, 1.0);
+    q *= f;  // e^f - 1
+    const double2 t = *reinterpret_cast<const double2 *>(tab + 2 * (n & 63));
+    return __builtin_ldexp(t.x + fma(t.x, q, t.y), n >> 6);
+}
+
+// sqrt(s) for a squared distance s >= 0 without a branch: s is raised by
+// 2^-1000 (below half an ulp of any s >= 2^-946, so other distances are
+// unchanged) so that the reciprocal square root never sees 0; coincident
+// points get distance 2^-500, whose covariance is the zero-distance value to
+// the last bit.  Then the coupled Newton refinement of sqrt_dist.
+__device__ __forceinline__ double sqrt_pos(double s) {
+    s += 0x1p-1000;
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y;
+    double h = 0.5 * y;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, s);
+    return fma(d, h, g);
+}
+
+// Matern covariance sigma2 * m(r) and, with WITH_D, its beta-derivative
+// sigma2 h(r) / beta (h as in matern_dbeta_r) for points a and b, using
+// exp_neg_tab.  The coordinates must be finite.
+template <int NU, bool WITH_D>
+__device__ __forceinline__ void matern_pair(double xa, double ya, double xb, double yb, const Params &P, double s2b,
+                                            const double *tab, double &c, double &db) {
+    const double dx = xa - xb, dy = ya - yb;
+    const double r = sqrt_pos(fma(dx, dx, dy * dy)) * P.inv_beta;
+    const double e = exp_neg_tab(r, tab);
+    if constexpr (NU == 0) {
+        c = P.sigma2 * e;
+        if constexpr (WITH_D) db = s2b * (r * e);
+    } else if constexpr (NU == 1) {
+        c = P.sigma2 * ((1.0 + r) * e);
+        if constexpr (WITH_D) db = s2b * ((r * r) * e);
+    } else {
+        c = P.sigma2 * ((1.0 + r * (1.0 + r * (1.0 / 3.0))) * e);
+        if constexpr (WITH_D) db = s2b * ((r * r) * (1.0 + r) * (1.0 / 3.0) * e);
+    }
 }
 
 // Matern covariance, Eq. (2), for half-integer smoothness in closed form.

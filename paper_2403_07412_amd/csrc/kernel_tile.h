@@ -47,12 +47,17 @@ __host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_co
 
 // Occupancy target (wavefronts per SIMD) the register allocation aims at.
 // Workgroups per CU are limited by LDS and by registers: each lane holds 8
-// VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 88
-// for the diagonal factorisation and addressing.
+// VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 96
+// for the diagonal factorisation, the covariance code and addressing.  Two
+// shapes were measured to need about 64 more and get that allowance.
+__host__ __device__ constexpr int tile_extra_vgprs(int T, int W) {
+    return ((T == 5 && W == 4) || (T == 7 && W == 8)) ? 64 : 0;
+}
+
 __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d) {
-    const int lds = (2 * T * 256 + 272 + 9 * 16 * T + 32) * 8;  // mirrors TileLds<T>::TOTAL
+    const int lds = (2 * T * 256 + 272 + 8 * 16 * T + 32 + 2 * kExpTableSize) * 8;  // TileLds<T>::BYTES
     const int blocks_lds = 163840 / lds;
-    const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 88;
+    const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 96 + tile_extra_vgprs(T, W);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
     const int blocks_regs = (wps_regs * 4) / W;      // workgroups per CU the registers allow
     int blocks = blocks_lds < blocks_regs ? blocks_lds : blocks_regs;
@@ -80,14 +85,14 @@ struct TileLds {
     static constexpr int XY = DIAG + 272;           // [KP][2]            coordinates
     static constexpr int ZV = XY + 2 * KP;          // [KP]               observations
     static constexpr int YP = ZV + KP;              // [KP]               factor row k+1
-    static constexpr int Q1 = YP + KP;              // [KP]               back-substitution vectors
-    static constexpr int Q2 = Q1 + KP;
-    static constexpr int U = Q2 + KP;
-    static constexpr int BH = U + KP;
-    static constexpr int SCAL = BH + KP;            // [16]               scalars: [0] L_kk
+    static constexpr int Q = YP + KP;               // [KP][2]            back-substitution right-hand sides
+    static constexpr int UB = Q + 2 * KP;           // [KP][2]            solutions (u, b)
+    static constexpr int SCAL = UB + 2 * KP;        // [16]               scalars: [0] L_kk
     static constexpr int RED = SCAL + 16;           // [16]               reductions
-    static constexpr int TOTAL = RED + 16;
+    static constexpr int EXPT = RED + 16;           // [64][2]            2^(j/64) as hi, lo for exp_neg_tab
+    static constexpr int TOTAL = EXPT + 2 * kExpTableSize;
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
+    static_assert(TOTAL == 2 * T * 256 + 272 + 8 * KP + 32 + 2 * kExpTableSize, "occupancy estimate out of date");
 };
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -193,15 +198,23 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Entry (a, b) of the augmented block given the covariance value `cov` of the
-// two points: nugget on the diagonal, the observation row k+1, identity padding.
-__device__ __forceinline__ double block_value(int a, int b, int k, double cov, const double *__restrict__ Z,
-                                              const Params &P) {
+// Entry (a, b) of the augmented block for rows or columns past k, given the
+// covariance entry v (nugget included): the observation row k+1 holds z of
+// the other index (1 in its diagonal, which the factorisation never uses),
+// the padding beyond it is the identity.
+__device__ __forceinline__ double augment_value(int a, int b, int k, double v, const double *__restrict__ Z) {
     const int hi = a > b ? a : b, lo = a > b ? b : a;
-    double v = cov + (a == b ? P.tau2 : 0.0);
     if (hi == k + 1) v = (lo == k + 1) ? 1.0 : Z[lo];
     if (hi > k + 1) v = (a == b) ? 1.0 : 0.0;
     return v;
+}
+
+// Stores a diagonal tile (T-layout registers) row-major into the DIAG area.
+template <int T>
+__device__ __forceinline__ void store_diag(const dvec4 &v, double *smem) {
+    const int l = threadIdx.x % kWave, g = l / 16, j = l % 16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) smem[TileLds<T>::DIAG + j * 17 + 4 * r + g] = v[r];
 }
 
 // Factors diagonal tile t, which the calling wave has stored row-major in the
@@ -236,7 +249,7 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     double Wr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] = (j == 4 * r + g) ? 1.0 : 0.0;
-    double dk = 0.0, myinv = 1.0;
+    double mydiag = 1.0, myinv = 1.0;  // L[j][j] and its reciprocal, kept per lane as column j passes
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
@@ -246,9 +259,12 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
             inv = rsqrt_refined(piv);
             d = piv * inv;
         }
-        if (q == jk) dk = d;
         const double lq = R[q] * inv;                      // L[j][q] for rows below q
         myinv = (j == q) ? inv : myinv;
+        mydiag = (j == q) ? d : mydiag;
+        // take the selects here: sunk to the end they would keep all 16
+        // pivots and inverses live through the factorisation
+        asm volatile("" : "+v"(myinv), "+v"(mydiag));
         const double nlq_inv = (j > q) ? -(lq * inv) : 0.0;  // -L[j][q] / L[q][q]
         R[q] = (j > q) ? lq : ((j == q) ? d : 0.0);        // column q of L
 #pragma unroll
@@ -265,7 +281,7 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     });
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] *= myinv;
-    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = dk;
+    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = mydiag;
     if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
@@ -310,6 +326,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 
     __syncthreads();  // the previous conditional is done with smem
     // gather (Algorithm 1: s_{J_i}, y_{J_i}); indices are checked before use
+    // and non-finite inputs flag the conditional (the covariance code below
+    // assumes finite coordinates)
     for (int t = tid; t < KP; t += NT) {
         double x = 0.0, y = 0.0, zz = 0.0;
         if (t <= k) {
@@ -324,59 +342,61 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             x = p.x;
             y = p.y;
             zz = z[jj];
+            bad |= !(isfinite(x) && isfinite(y) && isfinite(zz));
         }
         XY[2 * t] = x;
         XY[2 * t + 1] = y;
         Z[t] = zz;
     }
+    if (tid < kExpTableSize) {
+        smem[Ls::EXPT + 2 * tid] = kExp2Frac64[tid].hi;
+        smem[Ls::EXPT + 2 * tid + 1] = kExp2Frac64[tid].lo;
+    }
     __syncthreads();
 
-    // covariance generation straight into the register tiles; with the
-    // gradient, dC/dbeta of the strictly lower part (rows <= k) is kept in
-    // dtile from the same exponential
+    // covariance generation straight into the register tiles.  Only tiles
+    // that reach past row k (the observation row and the identity padding)
+    // and diagonal tiles (the nugget) need per-entry cases; the branches on
+    // them are uniform over the wavefront.  With the gradient, dC/dbeta is
+    // kept in dtile from the same exponential when registers allow.
     constexpr bool KEEP_D = GRAD && keep_dbeta(T, W);
+    const double *ET = smem + Ls::EXPT;
     dvec4 tile[NTW];
     dvec4 dtile[KEEP_D ? NTW : 1];
     const double s2b = P.sigma2 * P.inv_beta;
 #pragma unroll
     for (int s = 0; s < NTW; ++s) {
-        if (SR(s) >= 0) {
-            const int a = 16 * SR(s) + j;
-            const double xa = XY[2 * a], ya = XY[2 * a + 1];
+        tile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
+        if constexpr (KEEP_D) dtile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
+        const int R_ = SR(s), C_ = SC(s);
+        if (R_ < 0) continue;
+        const int a = 16 * R_ + j;
+        const double xa = XY[2 * a], ya = XY[2 * a + 1];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int b = 16 * SC(s) + 4 * r + g;
-                const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
-                double cov, db;
-                if constexpr (KEEP_D) {
-                    matern_and_dbeta_r<NU>(rb, P.sigma2, s2b, cov, db);
-                    dtile[s][r] = (a > b && a <= k) ? db : 0.0;
-                } else {
-                    cov = matern_r<NU>(rb, P.sigma2);
-                }
-                tile[s][r] = block_value(a, b, k, cov, Z, P);
-            }
-        } else {
-            tile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
-            if constexpr (KEEP_D) dtile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < 4; ++r) {
+            const int b = 16 * C_ + 4 * r + g;
+            double cv, db;
+            matern_pair<NU, KEEP_D>(xa, ya, XY[2 * b], XY[2 * b + 1], P, s2b, ET, cv, db);
+            tile[s][r] = cv;
+            if constexpr (KEEP_D) dtile[s][r] = db;
         }
+        if (R_ == C_) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (a == 16 * C_ + 4 * r + g) tile[s][r] += P.tau2;
+        }
+        if (16 * R_ + 15 > k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[s][r] = augment_value(a, 16 * C_ + 4 * r + g, k, tile[s][r], Z);
+        }
+        if (R_ == 0 && C_ == 0) store_diag<T>(tile[s], smem);
     }
 
     // blocked right-looking Cholesky
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
-        // 1. diagonal tile t (already fully updated by its owner)
-        if (w == tile_index(T, t, t) % W) {
-            const int sd = tile_index(T, t, t) / W;
-#pragma unroll
-            for (int s = 0; s < NTW; ++s) {
-                if (s == sd) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) smem[Ls::DIAG + j * 17 + 4 * r + g] = tile[s][r];
-                }
-            }
-            bad |= factor_diag<T>(t, k, smem);
-        }
+        // 1. diagonal tile t: fully updated, and stored to DIAG by its owner
+        if (w == tile_index(T, t, t) % W) bad |= factor_diag<T>(t, k, smem);
         __syncthreads();
         // 2. tiles below: X = A Linv_t^T, published to the panel
         const double *Li = smem + Ls::LINV + t * 256 + l * 4;
@@ -401,6 +421,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xc[q], xr[q], tile[s], 0, 0, 0);
+                // the next diagonal tile is now final: hand it to the factorisation
+                if (SR(s) == t + 1 && SC(s) == t + 1) store_diag<T>(tile[s], smem);
             }
         }
     }
@@ -425,11 +447,13 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const double c = Lkk * Lkk;
         const double rr = wv / Lkk;
         const double half = 0.5 * (rr * rr - 1.0 / c);
-        double *Q1 = smem + Ls::Q1, *Q2 = smem + Ls::Q2, *U = smem + Ls::U, *BH = smem + Ls::BH;
+        // back substitution with L^T for both right-hand sides at once:
+        // Q holds (q_u, q_b) pairs, UB receives (u, b) pairs
+        double *Q = smem + Ls::Q, *UB = smem + Ls::UB;
         const double *YP = smem + Ls::YP;
         for (int t = tid; t < KP; t += NT) {
-            Q1[t] = (t < k) ? rr * YP[t] : (t == k ? half * Lkk : 0.0);
-            Q2[t] = (t == k) ? Lkk : 0.0;
+            Q[2 * t] = (t < k) ? rr * YP[t] : (t == k ? half * Lkk : 0.0);
+            Q[2 * t + 1] = (t == k) ? Lkk : 0.0;
         }
         __syncthreads();
 #pragma unroll 1
@@ -437,15 +461,12 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             if (w == tile_index(T, t, t) % W) {
                 __builtin_amdgcn_s_setprio(3);
                 const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
-                const double q1 = Q1[16 * t + j], q2 = Q2[16 * t + j];
+                const double2 q = *reinterpret_cast<const double2 *>(Q + 2 * (16 * t + j));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const double p1 = sum16(li[r] * q1);
-                    const double p2 = sum16(li[r] * q2);
-                    if (j == 0) {
-                        U[16 * t + 4 * r + g] = p1;
-                        BH[16 * t + 4 * r + g] = p2;
-                    }
+                    const double p1 = sum16(li[r] * q.x);
+                    const double p2 = sum16(li[r] * q.y);
+                    if (j == 0) *reinterpret_cast<double2 *>(UB + 2 * (16 * t + 4 * r + g)) = double2{p1, p2};
                 }
                 __builtin_amdgcn_s_setprio(0);
             }
@@ -453,47 +474,57 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
             for (int s = 0; s < NTW; ++s) {
                 if (SR(s) == t && SC(s) < t) {
-                    const double x1 = U[16 * t + j], x2 = BH[16 * t + j];
+                    const double2 x = *reinterpret_cast<const double2 *>(UB + 2 * (16 * t + j));
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const double p1 = sum16(tile[s][r] * x1);
-                        const double p2 = sum16(tile[s][r] * x2);
+                        const double p1 = sum16(tile[s][r] * x.x);
+                        const double p2 = sum16(tile[s][r] * x.y);
                         if (j == 0) {
-                            Q1[16 * SC(s) + 4 * r + g] -= p1;
-                            Q2[16 * SC(s) + 4 * r + g] -= p2;
+                            double2 *qq = reinterpret_cast<double2 *>(Q + 2 * (16 * SC(s) + 4 * r + g));
+                            const double2 old = *qq;
+                            *qq = double2{old.x - p1, old.y - p2};
                         }
                     }
                 }
             }
             __syncthreads();
         }
-        // dl/dtau2 = u^T b; dl/dbeta = sum_{a > b} D_ab (u_a b_b + u_b b_a)
+        // dl/dtau2 = u^T b; dl/dbeta = sum_{a > b} D_ab (u_a b_b + u_b b_a).
+        // u and b vanish past row k, so entries there add exact zeros; in a
+        // diagonal tile the symmetric pairs are both visited and weighted by
+        // one half, and D_aa (zero in exact arithmetic, about 2^-500 sigma2 /
+        // beta^2 after sqrt_pos) is set to zero.
         double ub = 0.0;
-        for (int t = tid; t <= k; t += NT) ub += U[t] * BH[t];
+        for (int t = tid; t <= k; t += NT) ub += UB[2 * t] * UB[2 * t + 1];
         double gb = 0.0;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
-            if (SR(s) >= 0) {
-                const int a = 16 * SR(s) + j;
-                const double ua = U[a], ba = BH[a];
-                if constexpr (KEEP_D) {
+            const int R_ = SR(s), C_ = SC(s);
+            if (R_ < 0 || 16 * R_ > k) continue;
+            const int a = 16 * R_ + j;
+            const double2 uba = *reinterpret_cast<const double2 *>(UB + 2 * a);
+            double acc = 0.0;
+            if constexpr (KEEP_D) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int b = 16 * SC(s) + 4 * r + g;
-                        gb = fma(dtile[s][r], ua * BH[b] + U[b] * ba, gb);
-                    }
-                } else {
-                    const double xa = XY[2 * a], ya = XY[2 * a + 1];
+                for (int r = 0; r < 4; ++r) {
+                    const int b = 16 * C_ + 4 * r + g;
+                    const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * b);
+                    const double db = (a == b) ? 0.0 : dtile[s][r];
+                    acc = fma(db, fma(uba.x, ubb.y, ubb.x * uba.y), acc);
+                }
+            } else {
+                const double xa = XY[2 * a], ya = XY[2 * a + 1];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int b = 16 * SC(s) + 4 * r + g;
-                        if (a > b && a <= k) {
-                            const double rb = dist2d(xa, ya, XY[2 * b], XY[2 * b + 1]) * P.inv_beta;
-                            gb += matern_dbeta_r<NU>(rb, s2b) * (ua * BH[b] + U[b] * ba);
-                        }
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int b = 16 * C_ + 4 * r + g;
+                    const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * b);
+                    double cv, db;
+                    matern_pair<NU, true>(xa, ya, XY[2 * b], XY[2 * b + 1], P, s2b, ET, cv, db);
+                    db = (a == b) ? 0.0 : db;
+                    acc = fma(db, fma(uba.x, ubb.y, ubb.x * uba.y), acc);
                 }
             }
+            gb += (R_ == C_) ? 0.5 * acc : acc;
         }
         ub = block_sum<W>(ub, smem + Ls::RED);
         gb = block_sum<W>(gb, smem + Ls::RED);
