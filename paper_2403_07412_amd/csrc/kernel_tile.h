@@ -155,14 +155,6 @@ __device__ __forceinline__ void fma_bcast_row_self(double &acc, double w) {
                      : "v"(w), "i"(SRC));
 }
 
-// 32-bit DPP move of both halves of a double (any DPP control).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
 // compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -172,25 +164,20 @@ __device__ __forceinline__ void static_for(F &&f) {
     }
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate y (relative error near 2^-24)
+// and one third-order correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2.  The
+// residual e is formed without rounding loss (x y split into h + hl), so
+// the result is within about half an ulp; five dependent steps where two
+// Newton steps take six.
 __device__ __forceinline__ double rsqrt_refined(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = x * y;
+    const double hl = fma(x, y, -h);  // x y = h + hl exactly
+    const double e = fma(-hl, y, fma(-h, y, 1.0));
+    const double p = fma(e, 0.375, 0.5);
+    return fma(y * e, p, y);
 }
 
-__device__ __forceinline__ double sum16(double v) {
-    // sum over the 16 lanes of a row with DPP: pairs, quads, half rows, rows.
-    // Every lane adds the same partial sums (a + b == b + a), so all 16 lanes
-    // hold bitwise the same total.
-    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
-    return v;
-}
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -217,12 +204,28 @@ __device__ __forceinline__ void store_diag(const dvec4 &v, double *smem) {
     for (int r = 0; r < 4; ++r) smem[TileLds<T>::DIAG + j * 17 + 4 * r + g] = v[r];
 }
 
+// Rewrites Linv_t in the LINV area from T-layout (lane (g, j), register r:
+// Linv[j][4r + g]) to N-layout (lane (g, n), register r: Linv[4r + g][n]),
+// by the wave that owns it.  The four reads of every lane complete before
+// any write is issued, so the rewrite in place is safe within the wave.
+template <int T>
+__device__ __forceinline__ void linv_to_nlayout(int t, double *smem) {
+    const int l = threadIdx.x % kWave, g = l / 16, j = l % 16;
+    double *Lt = smem + TileLds<T>::LINV + t * 256;
+    const dvec4 v = *reinterpret_cast<const dvec4 *>(Lt + l * 4);
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Lt[(16 * (j % 4) + 4 * r + g) * 4 + j / 4] = v[r];
+}
+
 // Factors diagonal tile t, which the calling wave has stored row-major in the
 // DIAG area of LDS; publishes Linv_t (T-layout, lane-major) and records L_kk
-// and the part of factor row k+1 that falls in this tile.  Returns true on a
-// non-positive or non-finite pivot among rows <= k.
+// and the part of factor row k+1 that falls in this tile.  Rows past k (the
+// observation row and the padding) are not factored: their pivots count as
+// 1.  A pivot that is not positive and finite turns L_kk, and with it the
+// conditional's value, into NaN, which the caller reports.
 template <int T>
-__device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
+__device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     using Ls = TileLds<T>;
     int l = threadIdx.x % kWave;
     asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
@@ -237,7 +240,6 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     for (int c = 0; c < 16; ++c) R[c] = S[j * 17 + c];
     wave_lds_sync();
 
-    bool bad = false;
     const int base = 16 * t;
     const int jk = k - base;      // local index of row k (point i) if it lies in this tile
     const int jy = k + 1 - base;  // local index of row k+1 (observations) if it lies in this tile
@@ -253,31 +255,29 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
-        double inv = 1.0, d = 1.0;
-        if (base + q <= k) {
-            bad |= !(piv > 0.0) || !isfinite(piv);
-            inv = rsqrt_refined(piv);
-            d = piv * inv;
-        }
-        const double lq = R[q] * inv;                      // L[j][q] for rows below q
+        const double inv = (base + q <= k) ? rsqrt_refined(piv) : 1.0;
+        // column q of L: L[j][q] below the diagonal, L[q][q] = piv inv in
+        // lane q; the entries above the diagonal are never read
+        const double lq = R[q] * inv;
+        R[q] = lq;
+        // trailing update first, it carries the next pivot:
+        // R[c] -= L[j][q] L[c][q] with L[c][q] = lq of lane c
+        const double nlq = -lq;
+        static_for<q + 1, 16>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            fma_bcast_row<c, c == q + 1>(R[c], lq, nlq);
+        });
         myinv = (j == q) ? inv : myinv;
-        mydiag = (j == q) ? d : mydiag;
+        mydiag = (j == q) ? lq : mydiag;
         // take the selects here: sunk to the end they would keep all 16
         // pivots and inverses live through the factorisation
         asm volatile("" : "+v"(myinv), "+v"(mydiag));
-        const double nlq_inv = (j > q) ? -(lq * inv) : 0.0;  // -L[j][q] / L[q][q]
-        R[q] = (j > q) ? lq : ((j == q) ? d : 0.0);        // column q of L
+        const double nlq_inv = (j > q) ? nlq * inv : 0.0;  // -L[j][q] / L[q][q]
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (r == 0) fma_bcast_row_self<q, true>(Wr[r], nlq_inv);
             else fma_bcast_row_self<q, false>(Wr[r], nlq_inv);
         }
-        // trailing update of the tile: R[c] -= L[j][q] L[c][q], L[c][q] broadcast from lane c
-        const double nRq = -R[q];
-        static_for<q + 1, 16>([&](auto cc) {
-            constexpr int c = decltype(cc)::value;
-            fma_bcast_row<c, c == q + 1>(R[c], R[q], nRq);
-        });
     });
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] *= myinv;
@@ -291,7 +291,6 @@ __device__ __forceinline__ bool factor_diag(int t, int k, double *smem) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) Li[r] = Wr[r];
     __builtin_amdgcn_s_setprio(0);
-    return bad;
 }
 
 template <int T, int W, int NU, bool GRAD>
@@ -396,22 +395,35 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
         // 1. diagonal tile t: fully updated, and stored to DIAG by its owner
-        if (w == tile_index(T, t, t) % W) bad |= factor_diag<T>(t, k, smem);
+        if (w == tile_index(T, t, t) % W) factor_diag<T>(t, k, smem);
         __syncthreads();
-        // 2. tiles below: X = A Linv_t^T, published to the panel
+        // 2. tiles below: X = A Linv_t^T, published to the panel (T-layout).
+        // With the gradient the register copy is kept in N-layout (the same
+        // product with the operands swapped), the form the back substitution
+        // feeds to the matrix cores.
         const double *Li = smem + Ls::LINV + t * 256 + l * 4;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) == t && SR(s) > t) {
                 const dvec4 li = *reinterpret_cast<const dvec4 *>(Li);
                 dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+                dvec4 accn = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
-                tile[s] = acc;
+                for (int q = 0; q < 4; ++q) {
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
+                    if constexpr (GRAD) accn = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], li[q], accn, 0, 0, 0);
+                }
                 *reinterpret_cast<dvec4 *>(smem + Ls::PANEL + SR(s) * 256 + l * 4) = acc;
+                tile[s] = GRAD ? accn : acc;
             }
         }
         __syncthreads();
+        // Linv_t has served its last TRSM: the back substitution wants it in
+        // N-layout, rewritten in place by its owner (all reads of the wave
+        // complete before its writes)
+        if constexpr (GRAD) {
+            if (w == tile_index(T, t, t) % W) linv_to_nlayout<T>(t, smem);
+        }
         // 3. trailing update of the tiles right of column t
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
@@ -426,13 +438,23 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             }
         }
     }
-    // observation row k+1 from the tiles left of its diagonal tile
+    // observation row k+1 from the tiles left of its diagonal tile: in
+    // T-layout lane (g, jy) holds it, in N-layout register jy/4 of the lanes
+    // of row group jy%4
     const int ty = (k + 1) / 16, jy = (k + 1) % 16;
 #pragma unroll
     for (int s = 0; s < NTW; ++s) {
-        if (SR(s) == ty && SC(s) < ty && j == jy) {
+        if (SR(s) == ty && SC(s) < ty) {
+            if constexpr (GRAD) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) smem[Ls::YP + 16 * SC(s) + 4 * r + g] = tile[s][r];
+                for (int r = 0; r < 4; ++r)
+                    if (4 * r + g == jy) smem[Ls::YP + 16 * SC(s) + j] = tile[s][r];
+            } else {
+                if (j == jy) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) smem[Ls::YP + 16 * SC(s) + 4 * r + g] = tile[s][r];
+                }
+            }
         }
     }
     __syncthreads();
@@ -447,8 +469,15 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const double c = Lkk * Lkk;
         const double rr = wv / Lkk;
         const double half = 0.5 * (rr * rr - 1.0 / c);
-        // back substitution with L^T for both right-hand sides at once:
-        // Q holds (q_u, q_b) pairs, UB receives (u, b) pairs
+        // back substitution with L^T for both right-hand sides at once, on
+        // the matrix cores.  A 16 x 16 operand in N-layout (lane (g, n),
+        // register r holds M[4r + g][n]) enters a product as M^T when passed
+        // first and as M when passed second, and the product comes out in
+        // N-layout.  With the right-hand sides as columns 0 and 1 of X:
+        // x_t = Linv_t^T q_t, then q_C -= L_tC^T x_t for the tiles of row t;
+        // x_t leaves the first product already laid out as the second
+        // operand of the next.  Every wave forms x_t itself, so one barrier
+        // per step suffices.  Q holds (q_u, q_b) pairs, UB receives (u, b).
         double *Q = smem + Ls::Q, *UB = smem + Ls::UB;
         const double *YP = smem + Ls::YP;
         for (int t = tid; t < KP; t += NT) {
@@ -456,34 +485,29 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             Q[2 * t + 1] = (t == k) ? Lkk : 0.0;
         }
         __syncthreads();
+        const bool rhs_lane = j < 2;  // lanes of columns 0 and 1
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
-            if (w == tile_index(T, t, t) % W) {
-                __builtin_amdgcn_s_setprio(3);
-                const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
-                const double2 q = *reinterpret_cast<const double2 *>(Q + 2 * (16 * t + j));
+            const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
+            dvec4 xq;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double p1 = sum16(li[r] * q.x);
-                    const double p2 = sum16(li[r] * q.y);
-                    if (j == 0) *reinterpret_cast<double2 *>(UB + 2 * (16 * t + 4 * r + g)) = double2{p1, p2};
-                }
-                __builtin_amdgcn_s_setprio(0);
+            for (int q = 0; q < 4; ++q) xq[q] = rhs_lane ? Q[2 * (16 * t + 4 * q + g) + j] : 0.0;
+            dvec4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], xq[q], x, 0, 0, 0);
+            if (w == tile_index(T, t, t) % W && rhs_lane) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) UB[2 * (16 * t + 4 * r + g) + j] = x[r];
             }
-            __syncthreads();
 #pragma unroll
             for (int s = 0; s < NTW; ++s) {
                 if (SR(s) == t && SC(s) < t) {
-                    const double2 x = *reinterpret_cast<const double2 *>(UB + 2 * (16 * t + j));
+                    dvec4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double p1 = sum16(tile[s][r] * x.x);
-                        const double p2 = sum16(tile[s][r] * x.y);
-                        if (j == 0) {
-                            double2 *qq = reinterpret_cast<double2 *>(Q + 2 * (16 * SC(s) + 4 * r + g));
-                            const double2 old = *qq;
-                            *qq = double2{old.x - p1, old.y - p2};
-                        }
+                    for (int q = 0; q < 4; ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], x[q], d, 0, 0, 0);
+                    if (rhs_lane) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) Q[2 * (16 * SC(s) + 4 * r + g) + j] -= d[r];
                     }
                 }
             }
