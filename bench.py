@@ -39,6 +39,42 @@ METRIC = "Vecchia conditionals/sec (logL+grad, FP64) n=1M m=120; batched vs plai
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 GHz x 128 flop/clk
 
 
+# HBM traffic of the conditional kernel per launch on the default workload,
+# from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
+# KiB per dispatch) with --copy-probe: the probe's 512 MiB device copy reads
+# 262166.8 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
+# scale factors.  It describes the kernel sources it was measured on only, so
+# it is reported when their digest still matches (kernel_sources_digest).
+MEASURED_TRAFFIC = {
+    "sources_sha256": "778e69fe9d35643f2ac745215e7a1302220430966ad0227d854600562da043f6",
+    "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
+    "fetch_kib_raw": 8839842.6875, "fetch_factor": 524288.0 / 262166.8125,
+    "write_kib_raw": 4366825.25, "write_factor": 524288.0 / 524288.0,
+}
+
+
+def kernel_sources_digest() -> str:
+    """sha256 over the HIP sources and the C header, in sorted path order."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2403_07412_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "vecchia.h"))
+    for path in files:
+        h.update(os.path.relpath(path, ROOT).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes(workload: str, variant: str):
+    t = MEASURED_TRAFFIC
+    if t["workload"] != workload or t["variant"] != variant or t["sources_sha256"] != kernel_sources_digest():
+        return None
+    return (t["fetch_kib_raw"] * t["fetch_factor"] + t["write_kib_raw"] * t["write_factor"]) * 1024.0
+
+
 def la_flops_per_conditional(k: np.ndarray, with_grad: bool) -> np.ndarray:
     """Algorithmic dense-LA flops of one conditional with k neighbours (the paper's flop model, Sec. IV-C):
     POTRF k^3/3 + k^2/2 + k/6, two TRSVs 2k^2, the two dot products 4k; the gradient adds two
@@ -90,7 +126,9 @@ def main():
     ap.add_argument("--m", type=int, default=120)
     ap.add_argument("--variant", default="auto", help="plain form: kernel variant (auto, unblocked, tile_w1/2/4/8)")
     ap.add_argument("--form", default="both", choices=["both", "plain", "batched"])
-    ap.add_argument("--tune-sample", type=int, default=50000, help="points the autotuner times per variant")
+    ap.add_argument("--tune-sample", type=int, default=0,
+                    help="conditionals the autotuner times per variant (0: the whole field, so that every launch "
+                         "of the chosen kernel in a profile of this command has the full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, copy a 512 MiB device buffer once (a kernel of known traffic that scales "
@@ -156,7 +194,7 @@ def main():
         results["plain"] = (wall, launch_ms, out.item(), grad.cpu().numpy().copy(),
                             args.variant if args.variant != "auto" else v.vecchia_get_variant(f.m, True))
     if args.form in ("both", "batched"):
-        best, us = v.vecchia_autotune(locs, z, nbr, f.m, f.nu, theta, True, sample=args.tune_sample, reps=2)
+        best, us = v.vecchia_autotune(locs, z, nbr, f.m, f.nu, theta, True, sample=args.tune_sample or f.n, reps=2)
         print(f"# autotune m={f.m} grad: best variant {best}; us/point {us}", file=sys.stderr, flush=True)
         plan = v.BatchedPlan([(locs, z, nbr, f.m)], 1, f.nu, True)
         thetas = theta.reshape(1, 1, 3).contiguous()
@@ -208,6 +246,8 @@ def main():
                         "launch_ms": float(np.mean(pl)), "variant": names.get(pv, pv)}
     if args.traffic_kib is not None:
         rec["roofline"]["traffic"] = (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
+    else:
+        rec["roofline"]["traffic"] = measured_traffic_bytes(w.name, names.get(variant, variant))
     if args.copy_probe:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
