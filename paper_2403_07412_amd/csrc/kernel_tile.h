@@ -55,7 +55,7 @@ __host__ __device__ constexpr int tile_extra_vgprs(int T, int W) {
 }
 
 __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d) {
-    const int lds = (2 * T * 256 + 272 + 8 * 16 * T + 32 + 2 * kExpTableSize) * 8;  // TileLds<T>::BYTES
+    const int lds = (2 * T * 256 + 272 + 8 * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds<T>::BYTES
     const int blocks_lds = 163840 / lds;
     const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 96 + tile_extra_vgprs(T, W);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
@@ -88,11 +88,11 @@ struct TileLds {
     static constexpr int Q = YP + KP;               // [KP][2]            back-substitution right-hand sides
     static constexpr int UB = Q + 2 * KP;           // [KP][2]            solutions (u, b)
     static constexpr int SCAL = UB + 2 * KP;        // [16]               scalars: [0] L_kk
-    static constexpr int RED = SCAL + 16;           // [16]               reductions
-    static constexpr int EXPT = RED + 16;           // [64][2]            2^(j/64) as hi, lo for exp_neg_tab
+    static constexpr int RED = SCAL + 16;           // [2][32]            reductions (two values, up to 8 waves x 4 rows)
+    static constexpr int EXPT = RED + 64;           // [64][2]            2^(j/64) as hi, lo for exp_neg_tab
     static constexpr int TOTAL = EXPT + 2 * kExpTableSize;
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
-    static_assert(TOTAL == 2 * T * 256 + 272 + 8 * KP + 32 + 2 * kExpTableSize, "occupancy estimate out of date");
+    static_assert(TOTAL == 2 * T * 256 + 272 + 8 * KP + 80 + 2 * kExpTableSize, "occupancy estimate out of date");
 };
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -178,6 +178,47 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
     return fma(y * e, p, y);
 }
 
+
+// 64-bit DPP move of both halves of a double (any DPP control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of each row by DPP (pairs, quads, half rows, rows);
+// every lane of the row ends with the same bits.
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Workgroup sums of two values in a fixed order (rows, then rows of waves in
+// ascending order); every thread gets both totals.  `red` holds 2 * 4W doubles.
+template <int W>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
+    const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    a = row_sum16(a);
+    b = row_sum16(b);
+    __syncthreads();
+    if (l % 16 == 0) {
+        red[4 * w + l / 16] = a;
+        red[4 * W + 4 * w + l / 16] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4 * W; ++i) {
+        sa += red[i];
+        sb += red[4 * W + i];
+    }
+    a = sa;
+    b = sb;
+}
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -550,8 +591,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             }
             gb += (R_ == C_) ? 0.5 * acc : acc;
         }
-        ub = block_sum<W>(ub, smem + Ls::RED);
-        gb = block_sum<W>(gb, smem + Ls::RED);
+        block_sum2<W>(ub, gb, smem + Ls::RED);
         o.g2 = ub;
         o.g0 = (0.5 * (rr * rr * c - 1.0) - P.tau2 * ub) / P.sigma2;
         o.g1 = gb;
