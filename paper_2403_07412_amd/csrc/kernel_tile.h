@@ -228,11 +228,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Entry (a, b) of the augmented block for rows or columns past k, given the
 // covariance entry v (nugget included): the observation row k+1 holds z of
-// the other index (1 in its diagonal, which the factorisation never uses),
-// the padding beyond it is the identity.
+// the other index, the padding beyond it is the identity.  The diagonal of
+// row k+1 is never used as a result; 2^600 keeps its pivot positive (it
+// exceeds the squared norm of the row by far for any finite data), so the
+// factorisation needs no special case for it.
 __device__ __forceinline__ double augment_value(int a, int b, int k, double v, const double *__restrict__ Z) {
     const int hi = a > b ? a : b, lo = a > b ? b : a;
-    if (hi == k + 1) v = (lo == k + 1) ? 1.0 : Z[lo];
+    if (hi == k + 1) v = (lo == k + 1) ? 0x1p600 : Z[lo];
     if (hi > k + 1) v = (a == b) ? 1.0 : 0.0;
     return v;
 }
@@ -261,10 +263,12 @@ __device__ __forceinline__ void linv_to_nlayout(int t, double *smem) {
 
 // Factors diagonal tile t, which the calling wave has stored row-major in the
 // DIAG area of LDS; publishes Linv_t (T-layout, lane-major) and records L_kk
-// and the part of factor row k+1 that falls in this tile.  Rows past k (the
-// observation row and the padding) are not factored: their pivots count as
-// 1.  A pivot that is not positive and finite turns L_kk, and with it the
-// conditional's value, into NaN, which the caller reports.
+// and the part of factor row k+1 that falls in this tile.  Every row is
+// factored: the padding rows have pivot 1 and the observation row's diagonal
+// is 2^600 (augment_value), so their pivots are positive and nothing past row
+// k reaches rows up to k.  A pivot that is not positive and finite turns
+// L_kk, and with it the conditional's value, into NaN, which the caller
+// reports.
 template <int T>
 __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     using Ls = TileLds<T>;
@@ -296,7 +300,9 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
-        const double inv = (base + q <= k) ? rsqrt_refined(piv) : 1.0;
+        // no branch here: the pivot chain of the next column can then overlap
+        // the trailing update of this one
+        const double inv = rsqrt_refined(piv);
         // column q of L: L[j][q] below the diagonal, L[q][q] = piv inv in
         // lane q; the entries above the diagonal are never read
         const double lq = R[q] * inv;
