@@ -125,18 +125,18 @@ __device__ __forceinline__ double bcast_row(double v) {
     return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + SRC, 0xF, 0xF, false);
 }
 
-// acc += v(lane SRC of this lane's row) * w, one fused 64-bit DPP FMA.  With
-// NOP, two wait states precede it: a DPP source written by the instruction
-// just before needs them, and the compiler does not look inside inline
-// assembly for that hazard.
+// acc -= v(lane SRC of this lane's row) * w, one fused 64-bit DPP FMA with a
+// negated operand.  With NOP, two wait states precede it: a DPP source
+// written by the instruction just before needs them, and the compiler does
+// not look inside inline assembly for that hazard.
 template <int SRC, bool NOP>
-__device__ __forceinline__ void fma_bcast_row(double &acc, double v, double w) {
+__device__ __forceinline__ void fms_bcast_row(double &acc, double v, double w) {
     if constexpr (NOP)
-        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                      : "+v"(acc)
                      : "v"(v), "v"(w), "i"(SRC));
     else
-        asm volatile("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        asm volatile("v_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
                      : "+v"(acc)
                      : "v"(v), "v"(w), "i"(SRC));
 }
@@ -296,7 +296,7 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     double Wr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] = (j == 4 * r + g) ? 1.0 : 0.0;
-    double mydiag = 1.0, myinv = 1.0;  // L[j][j] and its reciprocal, kept per lane as column j passes
+    double myinv = 1.0;  // 1 / L[j][j], kept per lane as column j passes
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
@@ -309,17 +309,15 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
         R[q] = lq;
         // trailing update first, it carries the next pivot:
         // R[c] -= L[j][q] L[c][q] with L[c][q] = lq of lane c
-        const double nlq = -lq;
         static_for<q + 1, 16>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            fma_bcast_row<c, c == q + 1>(R[c], lq, nlq);
+            fms_bcast_row<c, c == q + 1>(R[c], lq, lq);
         });
         myinv = (j == q) ? inv : myinv;
-        mydiag = (j == q) ? lq : mydiag;
-        // take the selects here: sunk to the end they would keep all 16
-        // pivots and inverses live through the factorisation
-        asm volatile("" : "+v"(myinv), "+v"(mydiag));
-        const double nlq_inv = (j > q) ? nlq * inv : 0.0;  // -L[j][q] / L[q][q]
+        // take the select here: sunk to the end it would keep all 16
+        // inverses live through the factorisation
+        asm volatile("" : "+v"(myinv));
+        const double nlq_inv = (j > q) ? -(lq * inv) : 0.0;  // -L[j][q] / L[q][q]
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (r == 0) fma_bcast_row_self<q, true>(Wr[r], nlq_inv);
@@ -328,7 +326,9 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     });
 #pragma unroll
     for (int r = 0; r < 4; ++r) Wr[r] *= myinv;
-    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = mydiag;
+    // L_kk = 1 / (its refined reciprocal square-root pivot), within an ulp of
+    // pivot * rsqrt(pivot)
+    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = 1.0 / myinv;
     if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
