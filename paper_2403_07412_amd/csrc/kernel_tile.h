@@ -574,28 +574,33 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             if (R_ < 0 || 16 * R_ > k) continue;
             const int a = 16 * R_ + j;
             const double2 uba = *reinterpret_cast<const double2 *>(UB + 2 * a);
-            double acc = 0.0;
+            dvec4 db4;
             if constexpr (KEEP_D) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int b = 16 * C_ + 4 * r + g;
-                    const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * b);
-                    const double db = (a == b) ? 0.0 : dtile[s][r];
-                    acc = fma(db, fma(uba.x, ubb.y, ubb.x * uba.y), acc);
-                }
+                db4 = dtile[s];
             } else {
                 const double xa = XY[2 * a], ya = XY[2 * a + 1];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int b = 16 * C_ + 4 * r + g;
-                    const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * b);
                     double cv, db;
                     matern_pair<NU, true>(xa, ya, XY[2 * b], XY[2 * b + 1], P, s2b, ET, cv, db);
-                    db = (a == b) ? 0.0 : db;
-                    acc = fma(db, fma(uba.x, ubb.y, ubb.x * uba.y), acc);
+                    db4[r] = db;
                 }
             }
-            gb += (R_ == C_) ? 0.5 * acc : acc;
+            double w = 1.0;
+            if (R_ == C_) {  // wave-uniform: only diagonal tiles hold a == b
+                w = 0.5;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (a == 16 * C_ + 4 * r + g) db4[r] = 0.0;
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * (16 * C_ + 4 * r + g));
+                acc = fma(db4[r], fma(uba.x, ubb.y, ubb.x * uba.y), acc);
+            }
+            gb = fma(w, acc, gb);
         }
         block_sum2<W>(ub, gb, smem + Ls::RED);
         o.g2 = ub;
