@@ -260,6 +260,43 @@ int vecchia_batched_graph_destroy(vecchia_graph *graph);
 int vecchia_autotune(const vecchia_field *field, double nu, int32_t with_grad, const double *theta, int64_t sample,
                      int32_t reps, void *ws, size_t ws_bytes, void *stream, int32_t *best, double *us_per_point);
 
+/*
+ * Preprocessing before the likelihood: conditioning sets and ordering
+ * (Sec. IV-A/IV-B, the loop ahead of the likelihood in Algorithm 1).
+ *
+ * vecchia_knn: for each 0-based point i of locs (in the given order), the
+ * min(i, m) points j < i nearest to it, as the likelihood's `nbr` input.
+ *   locs  [dev] double[n][2], row-major, finite coordinates
+ *   n     number of points, n >= 0
+ *   m     set size, 0 <= m <= VECCHIA_MAX_M
+ *   nbr   [dev] int32[n][m], written: row i holds the indices ordered by
+ *         (squared distance, index) ascending, squared distances taken as
+ *         dx*dx + dy*dy with each product rounded; slots past min(i, m) = -1
+ *   ws    [dev] workspace of at least vecchia_knn_workspace_size(n) bytes
+ *   stream  HIP stream (hipStream_t, NULL = default); asynchronous
+ * Exact: equal to brute force over all j < i, independent of the device.
+ * The search uses a uniform grid over the bounding box (about two points per
+ * cell); non-finite coordinates give unspecified sets for the rows they touch.
+ * Returns VECCHIA_OK, VECCHIA_EINVAL (null pointers, n < 0, m < 0, n > 2^31 - 1),
+ * VECCHIA_EUNSUPPORTED (m > VECCHIA_MAX_M), VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+size_t vecchia_knn_workspace_size(int64_t n);
+int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * vecchia_morton_order: the Morton (Z-order) ordering of Sec. IV-A.  Each
+ * coordinate maps to a 16-bit cell floor((v - min) / (max - min) * 65536),
+ * clamped to [0, 65535], over the bounding box (zero extent: cell 0); the code
+ * interleaves x bits (even positions) and y bits (odd positions).
+ *   locs  [dev] double[n][2], finite
+ *   perm  [dev] int64[n], written: point indices by ascending code, ties by
+ *         ascending index (locs[perm[0]] comes first in the new order)
+ *   ws    [dev] at least vecchia_morton_workspace_size(n) bytes
+ * Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+size_t vecchia_morton_workspace_size(int64_t n);
+int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

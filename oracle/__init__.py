@@ -50,6 +50,10 @@ def _load():
         lib.oracle_matern.argtypes = [P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
         lib.oracle_sum.restype = ctypes.c_double
         lib.oracle_sum.argtypes = [P, ctypes.c_int64]
+        lib.oracle_knn_rows.restype = ctypes.c_int64
+        lib.oracle_knn_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int32]
+        lib.oracle_morton_order.restype = ctypes.c_int64
+        lib.oracle_morton_order.argtypes = [P, ctypes.c_int64, P]
         _lib = lib
     return _lib
 
@@ -127,3 +131,30 @@ def matern(d, nu: float, sigma2: float, beta: float, with_dbeta: bool = False):
 def compensated_sum(x) -> float:
     x = np.ascontiguousarray(x, dtype=np.float64).ravel()
     return float(_load().oracle_sum(x.ctypes.data, x.size))
+
+
+def knn_rows(locs, m: int, rows=None, threads: int = 0):
+    """Conditioning sets by brute force: for each row i, the min(i, m) nearest j < i by (squared distance,
+    index), -1 padded; returns [len(rows)][m] int32 (all rows by default)."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    n = locs.shape[0]
+    if locs.shape != (n, 2):
+        raise ValueError("locs must be [n][2]")
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((max(rows.size, 1), max(m, 1)), dtype=np.int32)
+    rc = _load().oracle_knn_rows(locs.ctypes.data, n, int(m), rows.ctypes.data, rows.size, out.ctypes.data,
+                                 int(threads))
+    if rc != 0:
+        raise OracleError(rc)
+    return out[:rows.size, :m]
+
+
+def morton_order(locs):
+    """Point indices in Morton (Z-order) order over the bounding box, ties by index."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    n = locs.shape[0]
+    perm = np.empty(max(n, 1), dtype=np.int64)
+    rc = _load().oracle_morton_order(locs.ctypes.data, n, perm.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return perm[:n]

@@ -332,3 +332,117 @@ void oracle_matern(const double *d, int64_t n, double nu, double sigma2, double 
 
 /* Neumaier sum exported for tests. */
 double oracle_sum(const double *x, int64_t n) { return neumaier(x, n, 1); }
+
+/*
+ * Conditioning sets by their definition (Sec. IV-B and the neighbour loop of
+ * Algorithm 1; ties and the short sets as read for this build): for each
+ * requested 0-based row i, the min(i, m) indices j < i closest to point i,
+ * ordered by (squared distance, index) ascending; slots past min(i, m) are -1.
+ * Squared distances are dx*dx + dy*dy, each product rounded (no
+ * contraction).  Brute force: every j < i is compared with the current m-th
+ * best and inserted into a sorted list when it beats it.
+ * out is [nrows][m].  Returns 0, or ORACLE_EINVAL / ORACLE_ENOMEM.
+ */
+int64_t oracle_knn_rows(const double *locs, int64_t n, int32_t m, const int64_t *rows, int64_t nrows,
+                        int32_t *out, int32_t nthreads) {
+    if (n < 0 || m < 0 || nrows < 0 || (nrows > 0 && (!rows || !out)) || (n > 0 && !locs)) return ORACLE_EINVAL;
+    for (int64_t r = 0; r < nrows; ++r)
+        if (rows[r] < 0 || rows[r] >= n) return ORACLE_EINVAL;
+    if (m == 0 || nrows == 0) return 0;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int failed = 0;
+#pragma omp parallel
+    {
+        double *bd = (double *)malloc((size_t)m * sizeof(double));
+        int32_t *bj = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        if (!bd || !bj) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t r = 0; r < nrows; ++r) {
+            if (!bd || !bj) continue;
+            const int64_t i = rows[r];
+            const int32_t k = (int32_t)(i < m ? i : m);
+            int32_t cnt = 0;
+            for (int64_t j = 0; j < i; ++j) {
+                const double dx = locs[2 * i] - locs[2 * j];
+                const double dy = locs[2 * i + 1] - locs[2 * j + 1];
+                const double d = dx * dx + dy * dy;
+                /* j ascends, so among equal distances an earlier j already wins */
+                if (cnt == k && !(d < bd[k - 1])) continue;
+                int32_t p = (cnt == k) ? k - 1 : cnt;
+                while (p > 0 && d < bd[p - 1]) {
+                    bd[p] = bd[p - 1];
+                    bj[p] = bj[p - 1];
+                    --p;
+                }
+                bd[p] = d;
+                bj[p] = (int32_t)j;
+                if (cnt < k) ++cnt;
+            }
+            for (int32_t t = 0; t < m; ++t) out[r * m + t] = (t < cnt) ? bj[t] : -1;
+        }
+        free(bd);
+        free(bj);
+    }
+    return failed ? ORACLE_ENOMEM : 0;
+}
+
+/*
+ * Morton (Z-order) ordering of the points (the ordering option of Sec. IV-A),
+ * as read for this build: each coordinate is mapped to a 16-bit cell index
+ * q = floor((x - min) / (max - min) * 65536) clamped to [0, 65535] over the
+ * bounding box (a zero extent maps to 0), the code interleaves the bits with
+ * x in the even and y in the odd positions, and perm lists the point indices
+ * by ascending code, ties by ascending index.  Returns 0 or ORACLE_EINVAL /
+ * ORACLE_ENOMEM.
+ */
+typedef struct {
+    uint32_t code;
+    int64_t idx;
+} morton_key_t;
+
+static int morton_cmp(const void *a, const void *b) {
+    const morton_key_t *x = (const morton_key_t *)a, *y = (const morton_key_t *)b;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+static uint32_t morton_cell(double v, double lo, double hi) {
+    const double w = hi - lo;
+    if (!(w > 0)) return 0;
+    double q = floor((v - lo) / w * 65536.0);
+    if (q < 0) q = 0;
+    if (q > 65535) q = 65535;
+    return (uint32_t)q;
+}
+
+int64_t oracle_morton_order(const double *locs, int64_t n, int64_t *perm) {
+    if (n < 0 || (n > 0 && (!locs || !perm))) return ORACLE_EINVAL;
+    if (n == 0) return 0;
+    double xmin = locs[0], xmax = locs[0], ymin = locs[1], ymax = locs[1];
+    for (int64_t i = 1; i < n; ++i) {
+        if (locs[2 * i] < xmin) xmin = locs[2 * i];
+        if (locs[2 * i] > xmax) xmax = locs[2 * i];
+        if (locs[2 * i + 1] < ymin) ymin = locs[2 * i + 1];
+        if (locs[2 * i + 1] > ymax) ymax = locs[2 * i + 1];
+    }
+    morton_key_t *keys = (morton_key_t *)malloc((size_t)n * sizeof(morton_key_t));
+    if (!keys) return ORACLE_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t qx = morton_cell(locs[2 * i], xmin, xmax);
+        const uint32_t qy = morton_cell(locs[2 * i + 1], ymin, ymax);
+        uint32_t code = 0;
+        for (int b = 0; b < 16; ++b) {
+            code |= ((qx >> b) & 1u) << (2 * b);
+            code |= ((qy >> b) & 1u) << (2 * b + 1);
+        }
+        keys[i].code = code;
+        keys[i].idx = i;
+    }
+    qsort(keys, (size_t)n, sizeof(morton_key_t), morton_cmp);
+    for (int64_t i = 0; i < n; ++i) perm[i] = keys[i].idx;
+    free(keys);
+    return 0;
+}

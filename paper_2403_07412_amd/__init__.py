@@ -114,6 +114,14 @@ def _load():
         lib.vecchia_autotune.restype = ctypes.c_int
         lib.vecchia_autotune.argtypes = [ctypes.POINTER(_Field), D, I32, P, I64, I32, P, SZ, P,
                                          ctypes.POINTER(I32), ctypes.POINTER(D)]
+        lib.vecchia_knn_workspace_size.restype = SZ
+        lib.vecchia_knn_workspace_size.argtypes = [I64]
+        lib.vecchia_knn.restype = ctypes.c_int
+        lib.vecchia_knn.argtypes = [P, I64, I32, P, P, SZ, P]
+        lib.vecchia_morton_workspace_size.restype = SZ
+        lib.vecchia_morton_workspace_size.argtypes = [I64]
+        lib.vecchia_morton_order.restype = ctypes.c_int
+        lib.vecchia_morton_order.argtypes = [P, I64, P, P, SZ, P]
         _lib = lib
     return _lib
 
@@ -461,3 +469,47 @@ def load_variant_table(path: str) -> None:
     for key, grad in (("value", False), ("grad", True)):
         for m, var in enumerate(data[key]):
             vecchia_set_variant(m, grad, int(var))
+
+
+# ------------------------------------------------------------- preprocessing
+def vecchia_knn_workspace_size(n: int) -> int:
+    return int(_load().vecchia_knn_workspace_size(int(n)))
+
+
+def vecchia_knn(locs, m: int, out=None, ws=None, stream=None):
+    """Conditioning sets on the GPU: int32 [n][m], row i = the min(i, m) nearest points j < i by
+    (squared distance, index), -1 padded.  locs: float64 [n][2] device tensor."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be float64 [n][2]")
+    _dev_check(locs)
+    n = locs.shape[0]
+    if out is None:
+        out = torch.empty((n, max(m, 0)), dtype=torch.int32, device=locs.device)
+    if tuple(out.shape) != (n, m) or out.dtype != torch.int32:
+        raise ValueError("out must be int32 [n][m]")
+    _dev_check(out)
+    need = vecchia_knn_workspace_size(n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
+    rc = _load().vecchia_knn(_ptr(locs), n, int(m), _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_knn")
+    return out
+
+
+def vecchia_morton_order(locs, out=None, ws=None, stream=None):
+    """Morton (Z-order) permutation of the points: int64 [n], ties by index."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be float64 [n][2]")
+    _dev_check(locs)
+    n = locs.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=locs.device)
+    if tuple(out.shape) != (n,) or out.dtype != torch.int64:
+        raise ValueError("out must be int64 [n]")
+    _dev_check(out)
+    need = int(_load().vecchia_morton_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
+    rc = _load().vecchia_morton_order(_ptr(locs), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_morton_order")
+    return out

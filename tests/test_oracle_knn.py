@@ -1,0 +1,98 @@
+"""Pins of the oracle's conditioning sets (Sec. IV-B) and Morton ordering (Sec. IV-A).
+
+The brute-force neighbour oracle is checked against hand-worked cases with
+exact ties, against scipy's k-d tree on random points (a library routine of
+its own), and against the workload generator's grid search; the Morton
+oracle against the quadrant structure of the Z curve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+
+def test_hand_worked_rows_with_ties():
+    # unit square corners, then its centre: the centre ties all four corners
+    locs = np.array([(0, 0), (1, 0), (0, 1), (1, 1), (0.5, 0.5)], dtype=float)
+    got = oracle.knn_rows(locs, 3)
+    want = np.array([[-1, -1, -1],
+                     [0, -1, -1],
+                     [0, 1, -1],
+                     [1, 2, 0],      # (1,1): (1,0) and (0,1) at distance 1 (index order), (0,0) at sqrt 2
+                     [0, 1, 2]])     # four ties at sqrt(1/2): the three lowest indices
+    np.testing.assert_array_equal(got, want)
+
+
+def test_hand_worked_duplicates_and_collinear():
+    # points on a line at x = 0, 3, 1, 3, 2 (a duplicate at 3)
+    locs = np.array([(0, 0), (3, 0), (1, 0), (3, 0), (2, 0)], dtype=float)
+    got = oracle.knn_rows(locs, 2, rows=[3, 4])
+    # row 3 (x=3): the earlier x=3 (distance 0), then x=1 (2) ties nothing; x=0 is 3 away
+    # row 4 (x=2): x=3 (index 1) and x=1 (index 2) both at 1, x=3 (index 3) also at 1 -> lowest two indices
+    np.testing.assert_array_equal(got, [[1, 2], [1, 2]])
+
+
+def test_matches_kdtree_on_random_points():
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(11)
+    n, m = 300, 12
+    locs = rng.uniform(size=(n, 2))
+    got = oracle.knn_rows(locs, m)
+    for i in range(1, n):
+        k = min(i, m)
+        d, idx = cKDTree(locs[:i]).query(locs[i], k=k)
+        idx = np.atleast_1d(idx)
+        np.testing.assert_array_equal(got[i, :k], idx, err_msg=f"row {i}")
+        assert (got[i, k:] == -1).all()
+        dd = np.sqrt(((locs[got[i, :k]] - locs[i]) ** 2).sum(1))
+        np.testing.assert_allclose(dd, np.atleast_1d(d), rtol=1e-14)
+
+
+def test_matches_grid_search_of_the_workload_generator():
+    rng = np.random.default_rng(12)
+    locs = wl.jittered_grid_locations(rng, 4096)[rng.permutation(4096)]
+    for m in (1, 7, 40):
+        np.testing.assert_array_equal(oracle.knn_rows(locs, m), wl.nearest_previous_neighbours(locs, m))
+
+
+def test_row_selection_and_errors():
+    rng = np.random.default_rng(13)
+    locs = rng.uniform(size=(50, 2))
+    full = oracle.knn_rows(locs, 5)
+    np.testing.assert_array_equal(oracle.knn_rows(locs, 5, rows=[49, 0, 17]), full[[49, 0, 17]])
+    assert oracle.knn_rows(locs, 0).shape == (50, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.knn_rows(locs, 5, rows=[50])
+
+
+def _quadrant_blocks(codes_order, locs, lo, hi, depth):
+    """Points of a square visited in Z order: lower-left, lower-right, upper-left, upper-right."""
+    if depth == 0 or len(codes_order) < 2:
+        return
+    mid = (lo + hi) / 2
+    q = (locs[codes_order, 0] >= mid[0]).astype(int) + 2 * (locs[codes_order, 1] >= mid[1]).astype(int)
+    assert (np.diff(q) >= 0).all(), "quadrants out of Z order"
+    for quad in range(4):
+        sel = codes_order[q == quad]
+        nlo = lo + np.array([quad % 2, quad // 2]) * (mid - lo)
+        _quadrant_blocks(sel, locs, nlo, nlo + (mid - lo), depth - 1)
+
+
+def test_morton_follows_the_z_curve():
+    rng = np.random.default_rng(14)
+    # points strictly inside cells of a 16 x 16 grid over [0, 1]^2 with both corners present
+    locs = (rng.integers(0, 16, size=(3000, 2)) + rng.uniform(0.1, 0.9, size=(3000, 2))) / 16
+    locs = np.vstack([[0.0, 0.0], locs, [1.0, 1.0]])
+    perm = oracle.morton_order(locs)
+    assert sorted(perm) == list(range(len(locs)))
+    _quadrant_blocks(perm, locs, np.array([0.0, 0.0]), np.array([1.0, 1.0]), 4)
+
+
+def test_morton_corners_and_ties():
+    locs = np.array([(1, 1), (0, 0), (1, 0), (0, 1), (0, 0)], dtype=float)
+    # codes: (0,0) -> 0 twice (indices 1 and 4), (1,0) -> x bits, (0,1) -> y bits, (1,1) -> all bits
+    np.testing.assert_array_equal(oracle.morton_order(locs), [1, 4, 2, 3, 0])
+    # a zero extent maps every coordinate to cell 0
+    flat = np.array([(0.3, 5.0), (0.1, 5.0), (0.2, 5.0)])
+    np.testing.assert_array_equal(oracle.morton_order(flat), [1, 2, 0])
