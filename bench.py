@@ -117,6 +117,37 @@ def cpu_baseline(field, with_grad: bool, target_s: float = 15.0):
                       f"({'value+gradient' if with_grad else 'value'}), {elapsed:.1f} s"}
 
 
+def preprocess_times(v, f, locs, stream, reps: int = 3):
+    """The workload's preprocessing on the GPU (conditioning sets, Morton ordering), best of `reps`
+    HIP-event timings, beside the CPU grid search that generated the benchmark's sets (16 threads)."""
+    import torch
+
+    import workloads as wl
+
+    def best_ms(fn):
+        ts = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return min(ts[1:])
+
+    nbr_out = torch.empty((f.n, f.m), dtype=torch.int32, device=locs.device)
+    kws = torch.empty(v.vecchia_knn_workspace_size(f.n), dtype=torch.uint8, device=locs.device)
+    knn_ms = best_ms(lambda: v.vecchia_knn(locs, f.m, out=nbr_out, ws=kws, stream=stream))
+    perm = torch.empty(f.n, dtype=torch.int64, device=locs.device)
+    morton_ms = best_ms(lambda: v.vecchia_morton_order(locs, out=perm, stream=stream))
+    same = bool(torch.equal(nbr_out.cpu(), torch.from_numpy(f.nbr)))
+    t0 = time.perf_counter()
+    wl.nearest_previous_neighbours(f.locs, f.m, min(os.cpu_count() or 1, 16))
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    return {"knn_ms": knn_ms, "morton_ms": morton_ms, "knn_cpu_grid_ms": cpu_ms,
+            "knn_cpu_threads": min(os.cpu_count() or 1, 16), "knn_equals_cpu_sets": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +161,8 @@ def main():
                     help="conditionals the autotuner times per variant (0: the whole field, so that every launch "
                          "of the chosen kernel in a profile of this command has the full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-preprocess", action="store_true",
+                    help="skip timing the GPU conditioning-set search and Morton ordering of the workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, copy a 512 MiB device buffer once (a kernel of known traffic that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -255,6 +288,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if not args.no_preprocess:
+        rec["preprocess"] = preprocess_times(v, f, locs, stream)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(f, True)
     print(json.dumps(rec), flush=True)
