@@ -297,6 +297,47 @@ int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws
 size_t vecchia_morton_workspace_size(int64_t n);
 int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Maximum-likelihood fit of theta = (sigma2, beta, tau2) at fixed nu, the use
+ * of the likelihood in Sec. V (the paper drives NLopt without derivatives;
+ * this driver uses the fused gradient).  Projected limited-memory BFGS in
+ * phi = log(theta) within [log lower, log upper], backtracking line search
+ * with the Armijo condition, objective -l/n.  An evaluation that fails (a
+ * non-positive pivot, non-finite value) counts as +infinity, so steps back
+ * off from it.  Stops when the largest free component of d(-l/n)/dphi is
+ * below gtol, after three steps that lower -l/n by at most
+ * ftol * max(1, |l|/n), after max_iter iterations, or when no step along the
+ * search direction decreases the objective.
+ */
+typedef struct vecchia_mle_options {
+    int32_t max_iter;  /* iterations (default 200) */
+    int32_t history;   /* BFGS pairs kept, 1..20 (default 8) */
+    double gtol;       /* default 1e-7 */
+    double ftol;       /* default 1e-13 */
+    double lower[3];   /* bounds on theta, 0 < lower <= upper, finite (defaults 1e-8, 1e-8, 1e-10) */
+    double upper[3];   /* (defaults 1e8 each) */
+} vecchia_mle_options;
+
+void vecchia_mle_default_options(vecchia_mle_options *opt);
+size_t vecchia_mle_workspace_size(int64_t n, int32_t m);
+
+/*
+ *   locs, z, nbr, n, m, nu  as vecchia_loglik_grad (device arrays), n >= 1
+ *   theta0      [host] double[3] start, each > 0 (clipped into the bounds)
+ *   options     [host] or NULL for the defaults
+ *   theta       [host] double[3] receives the estimate
+ *   loglik      [host] double or NULL: l at the estimate
+ *   grad        [host] double[3] or NULL: dl/dtheta at the estimate
+ *   iterations, evaluations  [host] int32 or NULL
+ *   ws          [dev] at least vecchia_mle_workspace_size(n, m) bytes
+ * Synchronises the stream after every evaluation.  Returns VECCHIA_OK,
+ * VECCHIA_EINVAL (bad arguments or options, or theta0 does not evaluate),
+ * VECCHIA_EUNSUPPORTED, VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
+                double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

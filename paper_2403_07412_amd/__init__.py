@@ -22,6 +22,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,6 +40,12 @@ class _Field(ctypes.Structure):
     """Mirror of struct vecchia_field."""
     _fields_ = [("locs", ctypes.c_void_p), ("z", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("m", ctypes.c_int32)]
+
+
+class MleOptions(ctypes.Structure):
+    """vecchia_mle_options."""
+    _fields_ = [("max_iter", ctypes.c_int32), ("history", ctypes.c_int32), ("gtol", ctypes.c_double),
+                ("ftol", ctypes.c_double), ("lower", ctypes.c_double * 3), ("upper", ctypes.c_double * 3)]
 
 
 class VecchiaError(RuntimeError):
@@ -122,6 +129,14 @@ def _load():
         lib.vecchia_morton_workspace_size.argtypes = [I64]
         lib.vecchia_morton_order.restype = ctypes.c_int
         lib.vecchia_morton_order.argtypes = [P, I64, P, P, SZ, P]
+        lib.vecchia_mle_default_options.restype = None
+        lib.vecchia_mle_default_options.argtypes = [ctypes.POINTER(MleOptions)]
+        lib.vecchia_mle_workspace_size.restype = SZ
+        lib.vecchia_mle_workspace_size.argtypes = [I64, I32]
+        lib.vecchia_mle.restype = ctypes.c_int
+        lib.vecchia_mle.argtypes = [P, P, P, I64, I32, D, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
+                                    ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
+                                    ctypes.POINTER(I32), P, SZ, P]
         _lib = lib
     return _lib
 
@@ -513,3 +528,31 @@ def vecchia_morton_order(locs, out=None, ws=None, stream=None):
     rc = _load().vecchia_morton_order(_ptr(locs), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "vecchia_morton_order")
     return out
+
+
+# ------------------------------------------------------------------ estimation
+def mle_default_options() -> MleOptions:
+    opt = MleOptions()
+    _load().vecchia_mle_default_options(ctypes.byref(opt))
+    return opt
+
+
+def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = None, ws=None, stream=None):
+    """Maximum-likelihood (sigma2, beta, tau2) at fixed nu.  Returns a dict with theta, loglik, grad,
+    iterations and evaluations."""
+    n = _as_inputs(locs, z, nbr, m)
+    need = int(_load().vecchia_mle_workspace_size(n, m))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=locs.device)
+    th0 = (ctypes.c_double * 3)(*[float(x) for x in theta0])
+    th = (ctypes.c_double * 3)()
+    gr = (ctypes.c_double * 3)()
+    ll = ctypes.c_double()
+    it = ctypes.c_int32()
+    ev = ctypes.c_int32()
+    rc = _load().vecchia_mle(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, int(m), float(nu), th0,
+                             ctypes.byref(options) if options is not None else None, th, ctypes.byref(ll), gr,
+                             ctypes.byref(it), ctypes.byref(ev), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_mle")
+    return {"theta": np.array(th[:]), "loglik": ll.value, "grad": np.array(gr[:]), "iterations": it.value,
+            "evaluations": ev.value}

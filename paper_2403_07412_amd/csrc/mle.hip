@@ -1,0 +1,230 @@
+// Maximum-likelihood estimation of (sigma2, beta, tau2) at fixed smoothness:
+// the use the Vecchia log-likelihood is built for (Sec. V fits the Matern
+// parameters by maximising it).  The paper drives a derivative-free NLopt
+// search; here the fused value + gradient evaluation feeds a projected
+// limited-memory BFGS in log-parameters, phi = log theta, inside bounds.
+//
+// Host code only: every evaluation is one vecchia_loglik_grad call on the
+// caller's stream, followed by a 40-byte read-back and a stream sync.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "vecchia.h"
+
+namespace {
+
+constexpr int kNp = 3;            // sigma2, beta, tau2
+constexpr int kMaxHistory = 20;
+constexpr size_t kScratch = 256;  // device scratch at the front of ws: out, grad, status, theta
+
+struct Eval {
+    double f;          // -l / n (+inf when the evaluation failed)
+    double g[kNp];     // d f / d phi
+    double ll;         // l
+    double gth[kNp];   // dl / dtheta
+    bool ok;
+};
+
+struct Problem {
+    const double *locs, *z;
+    const int32_t *nbr;
+    int64_t n;
+    int32_t m;
+    double nu;
+    char *ws;
+    size_t ws_bytes;
+    hipStream_t s;
+    int evals = 0;
+
+    int eval(const double *phi, Eval &e) {
+        double th[kNp];
+        for (int p = 0; p < kNp; ++p) th[p] = std::exp(phi[p]);
+        double *d_out = (double *)ws;
+        double *d_grad = d_out + 1;
+        int64_t *d_status = (int64_t *)(d_out + 4);
+        double *d_theta = d_out + 5;
+        if (hipMemcpyAsync(d_theta, th, sizeof(th), hipMemcpyHostToDevice, s) != hipSuccess) return VECCHIA_EHIP;
+        const int rc = vecchia_loglik_grad(locs, z, nbr, n, m, nu, d_theta, d_out, d_grad, d_status, ws + kScratch,
+                                           ws_bytes - kScratch, s);
+        if (rc != VECCHIA_OK) return rc;
+        double host[5];
+        int64_t status = 0;
+        if (hipMemcpyAsync(host, d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&status, d_status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return VECCHIA_EHIP;
+        ++evals;
+        e.ll = host[0];
+        e.ok = status == 0 && std::isfinite(host[0]);
+        const double scale = n > 0 ? 1.0 / (double)n : 1.0;
+        e.f = e.ok ? -host[0] * scale : INFINITY;
+        for (int p = 0; p < kNp; ++p) {
+            e.gth[p] = host[1 + p];
+            e.g[p] = -host[1 + p] * th[p] * scale;  // chain rule through theta = e^phi
+            e.ok = e.ok && std::isfinite(e.g[p]);
+        }
+        if (!e.ok) e.f = INFINITY;
+        return VECCHIA_OK;
+    }
+};
+
+double dot(const double *a, const double *b) {
+    double s = 0;
+    for (int p = 0; p < kNp; ++p) s += a[p] * b[p];
+    return s;
+}
+
+}  // namespace
+
+extern "C" void vecchia_mle_default_options(vecchia_mle_options *opt) {
+    if (!opt) return;
+    opt->max_iter = 200;
+    opt->history = 8;
+    opt->gtol = 1e-7;
+    opt->ftol = 1e-13;
+    opt->lower[0] = 1e-8;
+    opt->lower[1] = 1e-8;
+    opt->lower[2] = 1e-10;
+    opt->upper[0] = 1e8;
+    opt->upper[1] = 1e8;
+    opt->upper[2] = 1e8;
+}
+
+extern "C" size_t vecchia_mle_workspace_size(int64_t n, int32_t m) { return kScratch + vecchia_workspace_size(n, m); }
+
+extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                           const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
+                           double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes,
+                           void *stream) {
+    if (!theta0 || !theta || !locs || !z || (m > 0 && !nbr) || n < 1 || m < 0) return VECCHIA_EINVAL;
+    vecchia_mle_options opt;
+    if (options) {
+        opt = *options;
+    } else {
+        vecchia_mle_default_options(&opt);
+    }
+    if (opt.max_iter < 0 || opt.history < 1 || opt.history > kMaxHistory || !(opt.gtol >= 0) || !(opt.ftol >= 0))
+        return VECCHIA_EINVAL;
+    double lo[kNp], hi[kNp], phi[kNp];
+    for (int p = 0; p < kNp; ++p) {
+        if (!(opt.lower[p] > 0) || !(opt.upper[p] >= opt.lower[p]) || !std::isfinite(opt.upper[p]) ||
+            !(theta0[p] > 0) || !std::isfinite(theta0[p]))
+            return VECCHIA_EINVAL;
+        lo[p] = std::log(opt.lower[p]);
+        hi[p] = std::log(opt.upper[p]);
+        phi[p] = std::min(hi[p], std::max(lo[p], std::log(theta0[p])));
+    }
+    if (!ws || ws_bytes < vecchia_mle_workspace_size(n, m)) return VECCHIA_EWORKSPACE;
+    Problem pb{locs, z, nbr, n, m, nu, (char *)ws, ws_bytes, (hipStream_t)stream};
+
+    Eval cur;
+    int rc = pb.eval(phi, cur);
+    if (rc != VECCHIA_OK) return rc;
+    if (!cur.ok) return VECCHIA_EINVAL;  // the starting point itself does not evaluate
+
+    // limited-memory BFGS pairs (s, y) in phi
+    double S[kMaxHistory][kNp], Y[kMaxHistory][kNp], rho[kMaxHistory];
+    int hist = 0, head = 0, iter = 0, small_steps = 0;
+
+    // a variable is held at a bound while the gradient pushes it outward
+    auto free_var = [&](int p, const double *g) {
+        const double tol = 1e-12 * (1.0 + std::fabs(phi[p]));
+        if (phi[p] <= lo[p] + tol && g[p] > 0) return false;
+        if (phi[p] >= hi[p] - tol && g[p] < 0) return false;
+        return true;
+    };
+    auto proj_gnorm = [&](const double *g) {
+        double m_ = 0;
+        for (int p = 0; p < kNp; ++p)
+            if (free_var(p, g)) m_ = std::max(m_, std::fabs(g[p]));
+        return m_;
+    };
+
+    while (iter < opt.max_iter && proj_gnorm(cur.g) > opt.gtol) {
+        // search direction: two-loop recursion on the free variables
+        double d[kNp], q[kNp], alpha[kMaxHistory];
+        bool fr[kNp];
+        for (int p = 0; p < kNp; ++p) {
+            fr[p] = free_var(p, cur.g);
+            q[p] = fr[p] ? cur.g[p] : 0.0;
+        }
+        for (int t = 0; t < hist; ++t) {
+            const int idx = (head - 1 - t + kMaxHistory) % kMaxHistory;
+            alpha[t] = rho[idx] * dot(S[idx], q);
+            for (int p = 0; p < kNp; ++p) q[p] -= alpha[t] * Y[idx][p];
+        }
+        double gamma = 1.0;
+        if (hist > 0) {
+            const int last = (head - 1 + kMaxHistory) % kMaxHistory;
+            gamma = dot(S[last], Y[last]) / dot(Y[last], Y[last]);
+        }
+        for (int p = 0; p < kNp; ++p) q[p] *= gamma;
+        for (int t = hist - 1; t >= 0; --t) {
+            const int idx = (head - 1 - t + kMaxHistory) % kMaxHistory;
+            const double b = rho[idx] * dot(Y[idx], q);
+            for (int p = 0; p < kNp; ++p) q[p] += S[idx][p] * (alpha[t] - b);
+        }
+        for (int p = 0; p < kNp; ++p) d[p] = fr[p] ? -q[p] : 0.0;
+        double slope = dot(cur.g, d);
+        if (!(slope < 0)) {  // not a descent direction: restart from steepest descent
+            hist = 0;
+            for (int p = 0; p < kNp; ++p) d[p] = fr[p] ? -cur.g[p] : 0.0;
+            slope = dot(cur.g, d);
+            if (!(slope < 0)) break;
+        }
+        // first step without curvature information: at most one unit in phi
+        double step = 1.0;
+        if (hist == 0) {
+            double dmax = 0;
+            for (int p = 0; p < kNp; ++p) dmax = std::max(dmax, std::fabs(d[p]));
+            if (dmax > 1.0) step = 1.0 / dmax;
+        }
+        // projected backtracking line search with the Armijo condition
+        Eval nxt{};
+        double phin[kNp];
+        bool accepted = false;
+        for (int ls = 0; ls < 40; ++ls) {
+            for (int p = 0; p < kNp; ++p) phin[p] = std::min(hi[p], std::max(lo[p], phi[p] + step * d[p]));
+            double dphi[kNp];
+            for (int p = 0; p < kNp; ++p) dphi[p] = phin[p] - phi[p];
+            rc = pb.eval(phin, nxt);
+            if (rc != VECCHIA_OK) return rc;
+            if (nxt.ok && nxt.f <= cur.f + 1e-4 * dot(cur.g, dphi)) {
+                accepted = true;
+                break;
+            }
+            step *= 0.5;
+        }
+        if (!accepted) break;
+        double s[kNp], y[kNp];
+        for (int p = 0; p < kNp; ++p) {
+            s[p] = phin[p] - phi[p];
+            y[p] = nxt.g[p] - cur.g[p];
+        }
+        const double sy = dot(s, y);
+        if (sy > 1e-12 * std::sqrt(dot(s, s) * dot(y, y))) {
+            std::memcpy(S[head], s, sizeof(s));
+            std::memcpy(Y[head], y, sizeof(y));
+            rho[head] = 1.0 / sy;
+            head = (head + 1) % kMaxHistory;
+            hist = std::min(hist + 1, opt.history);
+        }
+        const double fdrop = cur.f - nxt.f;
+        std::memcpy(phi, phin, sizeof(phi));
+        cur = nxt;
+        ++iter;
+        small_steps = (fdrop <= opt.ftol * std::max(1.0, std::fabs(cur.f))) ? small_steps + 1 : 0;
+        if (small_steps >= 3) break;
+    }
+    for (int p = 0; p < kNp; ++p) theta[p] = std::exp(phi[p]);
+    if (loglik) *loglik = cur.ll;
+    if (grad)
+        for (int p = 0; p < kNp; ++p) grad[p] = cur.gth[p];
+    if (iterations) *iterations = iter;
+    if (evaluations) *evaluations = pb.evals;
+    return VECCHIA_OK;
+}
