@@ -338,6 +338,27 @@ int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t
                 const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
                 double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Exact Gaussian-process log-likelihood, Eq. (1), for the KL divergence of
+ * Eq. (9): KL(N_0 || N_a) = l_0(theta; 0) - l_a(theta; 0), the exact minus
+ * the Vecchia log-likelihood at y = 0.  Accuracy harness, not the hot path:
+ * the n x n covariance (Matern closed forms of Eq. (2), nugget on the
+ * diagonal) is generated in the workspace and factored by rocSOLVER (dpotrf);
+ * l = -1/2 (n log 2 pi + log det Sigma + z^T Sigma^-1 z).
+ *   locs    [dev] double[n][2];  z [dev] double[n], or NULL for y = 0
+ *   n       1 <= n <= 65535
+ *   theta   [dev] double[3] (sigma2, beta, tau2);  nu in {0.5, 1.5, 2.5}
+ *   out     [dev] double[1];  status [dev] int64[1]: 0, VECCHIA_STATUS_THETA,
+ *           or the 1-based column of the first non-positive pivot (out = NaN)
+ *   ws      [dev] at least vecchia_exact_workspace_size(n) bytes (8 n^2 + small)
+ * rocBLAS/rocSOLVER may allocate scratch of their own.  Synchronises the
+ * stream.  Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED (n too
+ * large), VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+size_t vecchia_exact_workspace_size(int64_t n);
+int vecchia_exact_loglik(const double *locs, const double *z, int64_t n, double nu, const double *theta, double *out,
+                         int64_t *status, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,8 @@ def _load():
         lib.oracle_sum.argtypes = [P, ctypes.c_int64]
         lib.oracle_knn_rows.restype = ctypes.c_int64
         lib.oracle_knn_rows.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int32]
+        lib.oracle_exact_loglik.restype = ctypes.c_int64
+        lib.oracle_exact_loglik.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, P, P]
         lib.oracle_morton_order.restype = ctypes.c_int64
         lib.oracle_morton_order.argtypes = [P, ctypes.c_int64, P]
         _lib = lib
@@ -158,3 +160,23 @@ def morton_order(locs):
     if rc != 0:
         raise OracleError(rc)
     return perm[:n]
+
+
+def exact_loglik(locs, z, nu: float, theta) -> float:
+    """Exact Gaussian log-likelihood of all points (dense Cholesky); z=None means y = 0."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    n = locs.shape[0]
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    zz = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
+    out = np.zeros(1)
+    rc = _load().oracle_exact_loglik(locs.ctypes.data, zz.ctypes.data if zz is not None else None, n, float(nu),
+                                     th.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return float(out[0])
+
+
+def kl_divergence(locs, nbr, m: int, nu: float, theta, threads: int = 0) -> float:
+    """Eq. (9): exact minus Vecchia log-likelihood at y = 0."""
+    n = np.asarray(locs).shape[0]
+    return exact_loglik(locs, None, nu, theta) - loglik(locs, np.zeros(n), nbr, m, nu, theta, threads=threads)

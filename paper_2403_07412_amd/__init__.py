@@ -133,6 +133,10 @@ def _load():
         lib.vecchia_mle_default_options.argtypes = [ctypes.POINTER(MleOptions)]
         lib.vecchia_mle_workspace_size.restype = SZ
         lib.vecchia_mle_workspace_size.argtypes = [I64, I32]
+        lib.vecchia_exact_workspace_size.restype = SZ
+        lib.vecchia_exact_workspace_size.argtypes = [I64]
+        lib.vecchia_exact_loglik.restype = ctypes.c_int
+        lib.vecchia_exact_loglik.argtypes = [P, P, I64, D, P, P, P, P, SZ, P]
         lib.vecchia_mle.restype = ctypes.c_int
         lib.vecchia_mle.argtypes = [P, P, P, I64, I32, D, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
                                     ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
@@ -556,3 +560,29 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
     _check(rc, "vecchia_mle")
     return {"theta": np.array(th[:]), "loglik": ll.value, "grad": np.array(gr[:]), "iterations": it.value,
             "evaluations": ev.value}
+
+
+# ------------------------------------------------------------- KL harness
+def vecchia_exact_loglik(locs, z, nu: float, theta, stream=None):
+    """Exact log-likelihood (dense Cholesky on the GPU); z=None means y = 0.  Returns (out, status)."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be float64 [n][2]")
+    _dev_check(locs, z, theta)
+    n = locs.shape[0]
+    ws = torch.empty(int(_load().vecchia_exact_workspace_size(n)), dtype=torch.uint8, device=locs.device)
+    out = torch.empty(1, dtype=torch.float64, device=locs.device)
+    status = torch.empty(1, dtype=torch.int64, device=locs.device)
+    rc = _load().vecchia_exact_loglik(_ptr(locs), _ptr(z), n, float(nu), _ptr(theta), _ptr(out), _ptr(status),
+                                      _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_exact_loglik")
+    return out, status
+
+
+def kl_divergence(locs, nbr, m: int, nu: float, theta, stream=None) -> float:
+    """Eq. (9): KL(N_0 || N_a) = l_0(theta; 0) - l_a(theta; 0), exact minus Vecchia log-likelihood at y = 0."""
+    zero = torch.zeros(locs.shape[0], dtype=torch.float64, device=locs.device)
+    ex, st = vecchia_exact_loglik(locs, None, nu, theta, stream=stream)
+    va, st2 = vecchia_loglik(locs, zero, nbr, m, nu, theta, stream=stream)
+    raise_on_status(st)
+    raise_on_status(st2)
+    return float(ex.item() - va.item())

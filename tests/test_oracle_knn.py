@@ -96,3 +96,35 @@ def test_morton_corners_and_ties():
     # a zero extent maps every coordinate to cell 0
     flat = np.array([(0.3, 5.0), (0.1, 5.0), (0.2, 5.0)])
     np.testing.assert_array_equal(oracle.morton_order(flat), [1, 2, 0])
+
+
+# ---- exact likelihood and the KL divergence of Eq. (9) ----------------------
+
+def test_exact_loglik_matches_lapack_on_a_bessel_covariance():
+    """Independent covariance (scipy's Bessel K form of Eq. (2)) and LAPACK's factorisation."""
+    rng = np.random.default_rng(15)
+    n = 300
+    locs = rng.uniform(size=(n, 2))
+    for nu, theta in ((0.5, (1.3, 0.1, 0.01)), (1.5, (0.7, 0.05, 1e-3)), (2.5, (2.0, 0.08, 0.05))):
+        d = np.sqrt(((locs[:, None, :] - locs[None, :, :]) ** 2).sum(-1))
+        cov = wl.matern_bessel(d, nu, theta[0], theta[1]) + theta[2] * np.eye(n)
+        sign, logdet = np.linalg.slogdet(cov)
+        z = rng.standard_normal(n)
+        want = -0.5 * (n * np.log(2 * np.pi) + logdet + z @ np.linalg.solve(cov, z))
+        want0 = -0.5 * (n * np.log(2 * np.pi) + logdet)
+        assert abs(oracle.exact_loglik(locs, z, nu, theta) - want) <= 1e-10 * abs(want)
+        assert abs(oracle.exact_loglik(locs, None, nu, theta) - want0) <= 1e-10 * abs(want0)
+
+
+def test_kl_is_zero_for_full_sets_and_decreases_with_m():
+    rng = np.random.default_rng(16)
+    n = 400
+    locs = rng.uniform(size=(n, 2))
+    theta = (1.0, 0.1, 1e-3)
+    kls = []
+    for m in (1, 5, 15, 40):
+        kls.append(oracle.kl_divergence(locs, wl.nearest_previous_neighbours(locs, m), m, 1.5, theta))
+    assert all(k > 0 for k in kls)
+    assert all(a >= b for a, b in zip(kls, kls[1:]))  # nested nearest-neighbour sets (Eq. (9) >= 0, monotone)
+    full = oracle.kl_divergence(locs, wl.nearest_previous_neighbours(locs, n - 1), n - 1, 1.5, theta)
+    assert abs(full) <= 1e-9 * n
