@@ -343,10 +343,11 @@ int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t
  * Eq. (9): KL(N_0 || N_a) = l_0(theta; 0) - l_a(theta; 0), the exact minus
  * the Vecchia log-likelihood at y = 0.  Accuracy harness, not the hot path:
  * the n x n covariance (Matern closed forms of Eq. (2), nugget on the
- * diagonal) is generated in the workspace and factored by rocSOLVER (dpotrf);
- * l = -1/2 (n log 2 pi + log det Sigma + z^T Sigma^-1 z).
+ * diagonal) is generated in the workspace and factored as in
+ * vecchia_dense_logdet; l = -1/2 (n log 2 pi + log det Sigma + z^T Sigma^-1 z).
  *   locs    [dev] double[n][2];  z [dev] double[n], or NULL for y = 0
- *   n       1 <= n <= 65535
+ *   n       1 <= n <= 2^30; in practice the 8 n^2-byte workspace bounds it
+ *           (n = 180,000 needs 259 GB)
  *   theta   [dev] double[3] (sigma2, beta, tau2);  nu in {0.5, 1.5, 2.5}
  *   out     [dev] double[1];  status [dev] int64[1]: 0, VECCHIA_STATUS_THETA,
  *           or the 1-based column of the first non-positive pivot (out = NaN)
@@ -357,6 +358,28 @@ int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t
  */
 size_t vecchia_exact_workspace_size(int64_t n);
 int vecchia_exact_loglik(const double *locs, const double *z, int64_t n, double nu, const double *theta, double *out,
+                         int64_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Log-determinant (and optionally z^T A^-1 z) of a dense symmetric positive
+ * definite matrix: the two terms of the Gaussian log-density of Eq. (1).  A is
+ * overwritten by its Cholesky factor (lower triangle; the strict upper
+ * triangle is not read) by a left-looking blocked factorisation: 1024-column
+ * diagonal blocks factored by rocSOLVER, panel updates by rocBLAS GEMM calls
+ * whose inner dimension is at most 8192, panel solves by rocBLAS TRSM.
+ *   A       [dev] double, column-major, n x n with leading dimension lda >= n
+ *   z       [dev] double[n] or NULL;  quad [dev] double[1], required with z
+ *   logdet  [dev] double[1]
+ *   status  [dev] int64[1]: 0, or the 1-based column of the first
+ *           non-positive pivot, or n when a result is not finite (then
+ *           logdet and quad are NaN)
+ *   ws      [dev] at least vecchia_dense_logdet_workspace_size(n) bytes
+ * Synchronises the stream.  Returns VECCHIA_OK, VECCHIA_EINVAL,
+ * VECCHIA_EUNSUPPORTED (n or lda above 2^30), VECCHIA_EWORKSPACE or
+ * VECCHIA_EHIP.
+ */
+size_t vecchia_dense_logdet_workspace_size(int64_t n);
+int vecchia_dense_logdet(double *A, int64_t n, int64_t lda, const double *z, double *logdet, double *quad,
                          int64_t *status, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus

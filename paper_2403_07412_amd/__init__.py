@@ -137,6 +137,10 @@ def _load():
         lib.vecchia_exact_workspace_size.argtypes = [I64]
         lib.vecchia_exact_loglik.restype = ctypes.c_int
         lib.vecchia_exact_loglik.argtypes = [P, P, I64, D, P, P, P, P, SZ, P]
+        lib.vecchia_dense_logdet_workspace_size.restype = SZ
+        lib.vecchia_dense_logdet_workspace_size.argtypes = [I64]
+        lib.vecchia_dense_logdet.restype = ctypes.c_int
+        lib.vecchia_dense_logdet.argtypes = [P, I64, I64, P, P, P, P, P, SZ, P]
         lib.vecchia_mle.restype = ctypes.c_int
         lib.vecchia_mle.argtypes = [P, P, P, I64, I32, D, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
                                     ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
@@ -576,6 +580,61 @@ def vecchia_exact_loglik(locs, z, nu: float, theta, stream=None):
                                       _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "vecchia_exact_loglik")
     return out, status
+
+
+def vecchia_dense_logdet(A, z=None, stream=None):
+    """log det A (and z^T A^-1 z with z) of an SPD float64 [n][n] device tensor, factored in place.
+
+    A is read as column-major with leading dimension A.stride(0) when
+    A.stride(1) == 1 (a row-major symmetric matrix is its own transpose),
+    so any contiguous symmetric tensor works.  Returns (logdet, quad or None, status).
+    """
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or A.stride(1) != 1:
+        raise ValueError("A must be a float64 [n][n] tensor with unit column stride")
+    if z is not None and (z.dtype != torch.float64 or tuple(z.shape) != (A.shape[0],) or not z.is_contiguous()):
+        raise ValueError("z must be a contiguous float64 [n]")
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    _dev_check(z)
+    n = A.shape[0]
+    ws = torch.empty(int(_load().vecchia_dense_logdet_workspace_size(n)), dtype=torch.uint8, device=A.device)
+    logdet = torch.empty(1, dtype=torch.float64, device=A.device)
+    quad = torch.empty(1, dtype=torch.float64, device=A.device) if z is not None else None
+    status = torch.empty(1, dtype=torch.int64, device=A.device)
+    rc = _load().vecchia_dense_logdet(_ptr(A), n, A.stride(0), _ptr(z), _ptr(logdet), _ptr(quad), _ptr(status),
+                                      _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_dense_logdet")
+    return logdet, quad, status
+
+
+def kl_curve(locs, ms, nu: float, theta, ordering: str = "random", seed: int = 0, stream=None) -> dict:
+    """KL divergence of Eq. (9) against the conditioning size, for one ordering of the points.
+
+    ordering: "random" (a seeded permutation), "morton" (vecchia_morton_order) or
+    "given" (as passed).  The exact log-likelihood is computed once; each m
+    takes GPU conditioning sets and one Vecchia evaluation at y = 0.
+    Returns {"ordering", "exact", "kl": {m: KL}}.
+    """
+    n = locs.shape[0]
+    if ordering == "random":
+        g = torch.Generator().manual_seed(seed)
+        locs = locs[torch.randperm(n, generator=g).to(locs.device)].contiguous()
+    elif ordering == "morton":
+        locs = locs[vecchia_morton_order(locs, stream=stream)].contiguous()
+    elif ordering != "given":
+        raise ValueError(f"unknown ordering {ordering!r}")
+    ex, st = vecchia_exact_loglik(locs, None, nu, theta, stream=stream)
+    raise_on_status(st)
+    exact = float(ex.item())
+    zero = torch.zeros(n, dtype=torch.float64, device=locs.device)
+    kl = {}
+    for m in ms:
+        nbr = vecchia_knn(locs, int(m), stream=stream)
+        va, st2 = vecchia_loglik(locs, zero, nbr, int(m), nu, theta, stream=stream)
+        raise_on_status(st2)
+        kl[int(m)] = exact - float(va.item())
+        del nbr
+    return {"ordering": ordering, "exact": exact, "kl": kl}
 
 
 def kl_divergence(locs, nbr, m: int, nu: float, theta, stream=None) -> float:
