@@ -17,7 +17,7 @@ import time
 import numpy as np
 import torch
 
-from . import VecchiaError, kl_curve
+from . import VecchiaError, VecchiaNumericalError, kl_curve
 
 # Table II: beta for effective range 0.1, 0.3, 0.8 at nu = 0.5, 1.5, 2.5 (the
 # (0.3, 2.5) entry as given in the captions of Figs. 5 and 6)
@@ -57,7 +57,7 @@ def main(argv=None) -> int:
             rec = {"n": args.n, "nu": nu, "beta": beta, "tau2": args.tau2, "effective_range": args.range}
             try:
                 rec.update(kl_curve(locs, args.m, nu, theta, ordering=ordering, seed=args.seed))
-            except VecchiaError as e:
+            except (VecchiaError, VecchiaNumericalError) as e:
                 rec.update({"ordering": ordering, "error": str(e)})
             torch.cuda.synchronize()
             rec["seconds"] = round(time.perf_counter() - t0, 2)
