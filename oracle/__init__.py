@@ -56,6 +56,21 @@ def _load():
         lib.oracle_exact_loglik.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, P, P]
         lib.oracle_morton_order.restype = ctypes.c_int64
         lib.oracle_morton_order.argtypes = [P, ctypes.c_int64, P]
+        I32, I64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        lib.oracle_terms_cov.restype = I64
+        lib.oracle_terms_cov.argtypes = [P, P, P, I64, I32, I32, I32, D, P, P, I64, P, P, I32]
+        lib.oracle_loglik_cov.restype = I64
+        lib.oracle_loglik_cov.argtypes = [P, P, P, I64, I32, I32, I32, D, P, P, P, I32]
+        lib.oracle_cov_values.restype = I64
+        lib.oracle_cov_values.argtypes = [P, I64, I32, I32, D, D, D, P, P]
+        lib.oracle_distances.restype = I64
+        lib.oracle_distances.argtypes = [P, P, I64, I32, P]
+        lib.oracle_knn_rows_metric.restype = I64
+        lib.oracle_knn_rows_metric.argtypes = [P, I64, I32, I32, P, I64, P, I32]
+        lib.oracle_knn_query.restype = I64
+        lib.oracle_knn_query.argtypes = [P, I64, P, I64, I32, I32, P, I32]
+        lib.oracle_predict.restype = I64
+        lib.oracle_predict.argtypes = [P, P, I64, P, I64, P, I32, I32, I32, D, P, P, P, I32]
         _lib = lib
     return _lib
 
@@ -83,6 +98,109 @@ def _prep(locs, z, nbr, m):
     else:
         nbr = np.zeros((max(n, 1), 1), dtype=np.int32)
     return locs, z, nbr, n
+
+
+# covariance models: family (Matern, Eq. (2); power exponential, Sec. V-C) and
+# metric (Euclidean on (x, y); great-circle on (longitude, latitude) degrees, km)
+MATERN, POWEXP = 0, 1
+EUCLIDEAN, GREAT_CIRCLE = 0, 1
+EARTH_RADIUS_KM = 6371.0
+
+
+def _cov(cov):
+    family, metric, smooth = cov
+    return int(family), int(metric), float(smooth)
+
+
+def terms_cov(locs, z, nbr, m: int, cov, theta, idx=None, with_grad: bool = False, threads: int = 0,
+              raise_on_fail: bool = True):
+    """Per-conditional l_i (and gradient) under a covariance model cov = (family, metric, smoothness)."""
+    locs, z, nbr, n = _prep(locs, z, nbr, m)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    if idx is None:
+        nidx = n
+        idx_p = None
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        nidx = idx.shape[0]
+        idx_p = idx.ctypes.data
+    ell = np.empty(max(nidx, 1), dtype=np.float64)
+    g = np.empty((max(nidx, 1), 3), dtype=np.float64) if with_grad else None
+    rc = _load().oracle_terms_cov(locs.ctypes.data, z.ctypes.data, nbr.ctypes.data, n, m, *_cov(cov),
+                                  th.ctypes.data, idx_p, nidx, ell.ctypes.data,
+                                  g.ctypes.data if g is not None else None, threads)
+    if rc < 0 or (rc > 0 and raise_on_fail):
+        raise OracleError(rc)
+    ell = ell[:nidx]
+    return (ell, g[:nidx]) if with_grad else ell
+
+
+def loglik_cov(locs, z, nbr, m: int, cov, theta, with_grad: bool = False, threads: int = 0):
+    """Vecchia log-likelihood (and gradient) under a covariance model cov = (family, metric, smoothness)."""
+    locs, z, nbr, n = _prep(locs, z, nbr, m)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    out = np.zeros(1)
+    g = np.zeros(3) if with_grad else None
+    rc = _load().oracle_loglik_cov(locs.ctypes.data, z.ctypes.data, nbr.ctypes.data, n, m, *_cov(cov),
+                                   th.ctypes.data, out.ctypes.data, g.ctypes.data if g is not None else None,
+                                   threads)
+    if rc != 0:
+        raise OracleError(rc)
+    return (float(out[0]), g) if with_grad else float(out[0])
+
+
+def cov_values(d, cov, sigma2: float, beta: float, with_dbeta: bool = False):
+    """The oracle's covariance values (and d/dbeta) of a model at distances d."""
+    d = np.ascontiguousarray(d, dtype=np.float64).ravel()
+    out = np.empty_like(d)
+    db = np.empty_like(d) if with_dbeta else None
+    rc = _load().oracle_cov_values(d.ctypes.data, d.size, *_cov(cov), float(sigma2), float(beta), out.ctypes.data,
+                                   db.ctypes.data if db is not None else None)
+    if rc != 0:
+        raise OracleError(rc)
+    return (out, db) if with_dbeta else out
+
+
+def distances(a, b, metric: int):
+    """Distances between matching rows of a and b ([n][2]): Euclidean, or great-circle km on (lon, lat) degrees."""
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 2)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1, 2)
+    out = np.empty(max(a.shape[0], 1))
+    rc = _load().oracle_distances(a.ctypes.data, b.ctypes.data, a.shape[0], int(metric), out.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return out[:a.shape[0]]
+
+
+def knn_query(ref, q, m: int, metric: int = EUCLIDEAN, threads: int = 0):
+    """Neighbour sets of prediction points: the min(n_ref, m) nearest reference points of each query
+    by (key, index), -1 padded; [nq][m] int32."""
+    ref = np.ascontiguousarray(ref, dtype=np.float64).reshape(-1, 2)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 2)
+    out = np.empty((max(q.shape[0], 1), max(m, 1)), dtype=np.int32)
+    rc = _load().oracle_knn_query(ref.ctypes.data, ref.shape[0], q.ctypes.data, q.shape[0], int(m), int(metric),
+                                  out.ctypes.data, int(threads))
+    if rc != 0:
+        raise OracleError(rc)
+    return out[:q.shape[0], :m]
+
+
+def predict(ref, zref, q, nbr, m: int, cov, theta, threads: int = 0, raise_on_fail: bool = True):
+    """Vecchia kriging: conditional mean and variance (of a new observation) at each prediction point."""
+    ref = np.ascontiguousarray(ref, dtype=np.float64).reshape(-1, 2)
+    zref = np.ascontiguousarray(zref, dtype=np.float64).ravel()
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 2)
+    nq = q.shape[0]
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32).reshape(nq, m) if m > 0 else np.zeros((max(nq, 1), 1),
+                                                                                           dtype=np.int32)
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(3)
+    mean = np.empty(max(nq, 1))
+    var = np.empty(max(nq, 1))
+    rc = _load().oracle_predict(ref.ctypes.data, zref.ctypes.data, ref.shape[0], q.ctypes.data, nq, nbr.ctypes.data,
+                                int(m), *_cov(cov), th.ctypes.data, mean.ctypes.data, var.ctypes.data, int(threads))
+    if rc < 0 or (rc > 0 and raise_on_fail):
+        raise OracleError(rc)
+    return mean[:nq], var[:nq]
 
 
 def terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_grad: bool = False, threads: int = 0,
@@ -135,17 +253,18 @@ def compensated_sum(x) -> float:
     return float(_load().oracle_sum(x.ctypes.data, x.size))
 
 
-def knn_rows(locs, m: int, rows=None, threads: int = 0):
-    """Conditioning sets by brute force: for each row i, the min(i, m) nearest j < i by (squared distance,
-    index), -1 padded; returns [len(rows)][m] int32 (all rows by default)."""
+def knn_rows(locs, m: int, rows=None, threads: int = 0, metric: int = EUCLIDEAN):
+    """Conditioning sets by brute force: for each row i, the min(i, m) nearest j < i by (key, index), -1
+    padded, the key being the squared distance (Euclidean) or the haversine value (great-circle); returns
+    [len(rows)][m] int32 (all rows by default)."""
     locs = np.ascontiguousarray(locs, dtype=np.float64)
     n = locs.shape[0]
     if locs.shape != (n, 2):
         raise ValueError("locs must be [n][2]")
     rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
     out = np.empty((max(rows.size, 1), max(m, 1)), dtype=np.int32)
-    rc = _load().oracle_knn_rows(locs.ctypes.data, n, int(m), rows.ctypes.data, rows.size, out.ctypes.data,
-                                 int(threads))
+    rc = _load().oracle_knn_rows_metric(locs.ctypes.data, n, int(m), int(metric), rows.ctypes.data, rows.size,
+                                        out.ctypes.data, int(threads))
     if rc != 0:
         raise OracleError(rc)
     return out[:rows.size, :m]

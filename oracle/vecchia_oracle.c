@@ -86,6 +86,71 @@ static double dist(const double *a, const double *b) {
     return sqrt(dx * dx + dy * dy);
 }
 
+/*
+ * Covariance model: family (0 Matern, Eq. (2); 1 power exponential, the
+ * real-data model of Sec. V-C) and metric (0 Euclidean on (x, y); 1
+ * great-circle on (longitude, latitude) in degrees, in kilometres).
+ * smooth is nu for Matern and alpha for the power exponential.
+ */
+typedef struct {
+    int family, metric;
+    double smooth;
+} cov_t;
+
+#define ORACLE_EARTH_RADIUS_KM 6371.0
+#define ORACLE_DEG2RAD 0.017453292519943295769236907684886
+
+/*
+ * Haversine value of two (lon, lat) points in degrees (Sec. V-C): with
+ * phi the latitudes and lambda the longitudes in radians,
+ *   hav(d / R) = hav(phi_a - phi_b) + cos phi_a cos phi_b hav(lambda_a - lambda_b),
+ * hav(t) = sin^2(t / 2).  Differences are taken in degrees before the
+ * conversion.  The result is clamped to [0, 1].
+ */
+static double haversine(const double *a, const double *b) {
+    const double dlat = (a[1] - b[1]) * ORACLE_DEG2RAD;
+    const double dlon = (a[0] - b[0]) * ORACLE_DEG2RAD;
+    const double s1 = sin(0.5 * dlat), s2 = sin(0.5 * dlon);
+    const double ca = cos(a[1] * ORACLE_DEG2RAD), cb = cos(b[1] * ORACLE_DEG2RAD);
+    double h = s1 * s1 + (ca * cb) * (s2 * s2);
+    if (h > 1.0) h = 1.0;
+    return h;
+}
+
+/* great-circle distance in km: d = 2 R asin(sqrt(h)) */
+static double gcd_km(const double *a, const double *b) {
+    return 2.0 * ORACLE_EARTH_RADIUS_KM * asin(sqrt(haversine(a, b)));
+}
+
+static double cov_dist(const cov_t *cv, const double *a, const double *b) {
+    return cv->metric == 1 ? gcd_km(a, b) : dist(a, b);
+}
+
+/* power exponential C(d) = sigma2 exp(-d^alpha / beta) and its beta-derivative C d^alpha / beta^2 */
+static double powexp(double d, double alpha, double sigma2, double beta) {
+    return sigma2 * exp(-pow(d, alpha) / beta);
+}
+
+static double powexp_dbeta(double d, double alpha, double sigma2, double beta) {
+    const double u = pow(d, alpha) / beta;
+    return sigma2 * exp(-u) * u / beta;
+}
+
+static double cov_fn(const cov_t *cv, double d, double sigma2, double beta) {
+    return cv->family == 1 ? powexp(d, cv->smooth, sigma2, beta) : matern(d, cv->smooth, sigma2, beta);
+}
+
+static double cov_dbeta(const cov_t *cv, double d, double sigma2, double beta) {
+    return cv->family == 1 ? powexp_dbeta(d, cv->smooth, sigma2, beta) : matern_dbeta(d, cv->smooth, sigma2, beta);
+}
+
+static int valid_cov(const cov_t *cv) {
+    if (cv->metric != 0 && cv->metric != 1) return 0;
+    if (cv->family == 0) return cv->smooth == 0.5 || cv->smooth == 1.5 || cv->smooth == 2.5;
+    if (cv->family == 1) return cv->smooth > 0.0 && cv->smooth <= 2.0;
+    return 0;
+}
+
 typedef struct {
     double *S, *L, *v, *yN, *vp, *yp, *a, *s, *Sp, *vpd;
 } work_t;
@@ -116,7 +181,7 @@ static void work_free(work_t *w) {
  * (or not finite).
  */
 static int conditional(const double *locs, const double *z, const int32_t *nbr_row, int64_t i, int k,
-                       double nu, double sigma2, double beta, double tau2, work_t *w, double *ell,
+                       const cov_t *cv, double sigma2, double beta, double tau2, work_t *w, double *ell,
                        double *g) {
     const double *si = locs + 2 * i;
     /* covariance generation (Algorithm 1, batched kernel step) */
@@ -124,9 +189,9 @@ static int conditional(const double *locs, const double *z, const int32_t *nbr_r
         const double *sa = locs + 2 * (int64_t)nbr_row[a];
         for (int b = 0; b < k; ++b) {
             const double *sb = locs + 2 * (int64_t)nbr_row[b];
-            w->S[a * k + b] = matern(dist(sa, sb), nu, sigma2, beta) + (a == b ? tau2 : 0.0);
+            w->S[a * k + b] = cov_fn(cv, cov_dist(cv, sa, sb), sigma2, beta) + (a == b ? tau2 : 0.0);
         }
-        w->v[a] = matern(dist(sa, si), nu, sigma2, beta);
+        w->v[a] = cov_fn(cv, cov_dist(cv, sa, si), sigma2, beta);
         w->yN[a] = z[nbr_row[a]];
     }
     double Sii = sigma2 + tau2;
@@ -185,16 +250,16 @@ static int conditional(const double *locs, const double *z, const int32_t *nbr_r
             const double *sa = locs + 2 * (int64_t)nbr_row[a];
             for (int b = 0; b < k; ++b) {
                 const double *sb = locs + 2 * (int64_t)nbr_row[b];
-                double d = dist(sa, sb);
+                double d = cov_dist(cv, sa, sb);
                 double val;
-                if (p == 0) val = matern(d, nu, sigma2, beta) / sigma2;
-                else if (p == 1) val = matern_dbeta(d, nu, sigma2, beta);
+                if (p == 0) val = cov_fn(cv, d, sigma2, beta) / sigma2;
+                else if (p == 1) val = cov_dbeta(cv, d, sigma2, beta);
                 else val = (a == b) ? 1.0 : 0.0;
                 w->Sp[a * k + b] = val;
             }
-            double di = dist(sa, si);
-            if (p == 0) w->vpd[a] = matern(di, nu, sigma2, beta) / sigma2;
-            else if (p == 1) w->vpd[a] = matern_dbeta(di, nu, sigma2, beta);
+            double di = cov_dist(cv, sa, si);
+            if (p == 0) w->vpd[a] = cov_fn(cv, di, sigma2, beta) / sigma2;
+            else if (p == 1) w->vpd[a] = cov_dbeta(cv, di, sigma2, beta);
             else w->vpd[a] = 0.0;
         }
         Siip = (p == 1) ? 0.0 : 1.0;
@@ -241,12 +306,14 @@ static int valid_nu(double nu) { return nu == 0.5 || nu == 1.5 || nu == 2.5; }
  * Returns 0; a negative error code for bad arguments; or (i+1) for the smallest
  * listed point i whose conditional failed (its outputs are NaN).
  */
-int64_t oracle_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
-                     const double *theta, const int64_t *idx, int64_t nidx, double *ell, double *grad,
-                     int32_t nthreads) {
+int64_t oracle_terms_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                         int32_t family, int32_t metric, double smooth, const double *theta, const int64_t *idx,
+                         int64_t nidx, double *ell, double *grad, int32_t nthreads) {
+    const cov_t cvs = {family, metric, smooth};
+    const cov_t *cv = &cvs;
     if (!locs || !z || !theta || !ell || n < 0 || m < 0 || (m > 0 && !nbr) || nidx < 0) return ORACLE_EINVAL;
     if (!idx && nidx != n) return ORACLE_EINVAL;
-    if (!valid_nu(nu) || !(theta[0] > 0) || !(theta[1] > 0) || !(theta[2] >= 0)) return ORACLE_EINVAL;
+    if (!valid_cov(cv) || !(theta[0] > 0) || !(theta[1] > 0) || !(theta[2] >= 0)) return ORACLE_EINVAL;
     for (int64_t t = 0; t < nidx; ++t) {
         int64_t i = idx ? idx[t] : t;
         if (i < 0 || i >= n) return ORACLE_EINVAL;
@@ -274,7 +341,7 @@ int64_t oracle_terms(const double *locs, const double *z, const int32_t *nbr, in
             int k = (int)(i < m ? i : m);
             double g[3] = {0, 0, 0};
             double e = 0.0;
-            int bad = conditional(locs, z, nbr + i * (int64_t)m, i, k, nu, theta[0], theta[1], theta[2], &w, &e,
+            int bad = conditional(locs, z, nbr + i * (int64_t)m, i, k, cv, theta[0], theta[1], theta[2], &w, &e,
                                   grad ? g : NULL);
             if (bad) {
                 e = NAN;
@@ -297,12 +364,21 @@ int64_t oracle_terms(const double *locs, const double *z, const int32_t *nbr, in
     return first_fail == INT64_MAX ? 0 : first_fail + 1;
 }
 
+/* Matern covariance with Euclidean distance (Eq. (2)): oracle_terms_cov with family 0, metric 0. */
+int64_t oracle_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                     const double *theta, const int64_t *idx, int64_t nidx, double *ell, double *grad,
+                     int32_t nthreads) {
+    if (!valid_nu(nu)) return ORACLE_EINVAL;
+    return oracle_terms_cov(locs, z, nbr, n, m, 0, 0, nu, theta, idx, nidx, ell, grad, nthreads);
+}
+
 /*
  * Whole log-likelihood: out[0] = sum_i l_i; grad[0..3) = sum_i dl_i/dp when grad != NULL.
  * Sums are Neumaier-compensated in ascending i.  Return value as oracle_terms.
  */
-int64_t oracle_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
-                      const double *theta, double *out, double *grad, int32_t nthreads) {
+int64_t oracle_loglik_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                          int32_t family, int32_t metric, double smooth, const double *theta, double *out,
+                          double *grad, int32_t nthreads) {
     if (!out || n < 0) return ORACLE_EINVAL;
     double *ell = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double *g = grad ? (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double)) : NULL;
@@ -310,7 +386,7 @@ int64_t oracle_loglik(const double *locs, const double *z, const int32_t *nbr, i
         free(ell); free(g);
         return ORACLE_ENOMEM;
     }
-    int64_t rc = oracle_terms(locs, z, nbr, n, m, nu, theta, NULL, n, ell, g, nthreads);
+    int64_t rc = oracle_terms_cov(locs, z, nbr, n, m, family, metric, smooth, theta, NULL, n, ell, g, nthreads);
     if (rc >= 0) {
         out[0] = neumaier(ell, n, 1);
         if (grad)
@@ -319,6 +395,32 @@ int64_t oracle_loglik(const double *locs, const double *z, const int32_t *nbr, i
     free(ell);
     free(g);
     return rc;
+}
+
+int64_t oracle_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                      const double *theta, double *out, double *grad, int32_t nthreads) {
+    if (!valid_nu(nu)) return ORACLE_EINVAL;
+    return oracle_loglik_cov(locs, z, nbr, n, m, 0, 0, nu, theta, out, grad, nthreads);
+}
+
+/* Covariance values and beta-derivatives of any model at distances d, for pins. */
+int64_t oracle_cov_values(const double *d, int64_t n, int32_t family, int32_t metric, double smooth, double sigma2,
+                          double beta, double *out, double *dbeta) {
+    const cov_t cv = {family, metric, smooth};
+    if (!valid_cov(&cv) || n < 0 || (n > 0 && (!d || !out))) return ORACLE_EINVAL;
+    for (int64_t t = 0; t < n; ++t) {
+        out[t] = cov_fn(&cv, d[t], sigma2, beta);
+        if (dbeta) dbeta[t] = cov_dbeta(&cv, d[t], sigma2, beta);
+    }
+    return 0;
+}
+
+/* Pairwise distances a[t] to b[t] (n pairs of points) under a metric, for pins. */
+int64_t oracle_distances(const double *a, const double *b, int64_t n, int32_t metric, double *out) {
+    if (n < 0 || (metric != 0 && metric != 1) || (n > 0 && (!a || !b || !out))) return ORACLE_EINVAL;
+    const cov_t cv = {0, metric, 0.5};
+    for (int64_t t = 0; t < n; ++t) out[t] = cov_dist(&cv, a + 2 * t, b + 2 * t);
+    return 0;
 }
 
 /* The covariance entries this oracle uses, exported so tests can pin them against Eq. (2). */
@@ -334,18 +436,56 @@ void oracle_matern(const double *d, int64_t n, double nu, double sigma2, double 
 double oracle_sum(const double *x, int64_t n) { return neumaier(x, n, 1); }
 
 /*
- * Conditioning sets by their definition (Sec. IV-B and the neighbour loop of
- * Algorithm 1; ties and the short sets as read for this build): for each
- * requested 0-based row i, the min(i, m) indices j < i closest to point i,
- * ordered by (squared distance, index) ascending; slots past min(i, m) are -1.
- * Squared distances are dx*dx + dy*dy, each product rounded (no
- * contraction).  Brute force: every j < i is compared with the current m-th
- * best and inserted into a sorted list when it beats it.
- * out is [nrows][m].  Returns 0, or ORACLE_EINVAL / ORACLE_ENOMEM.
+ * Ranking key of a candidate j for query point q: the squared Euclidean
+ * distance dx*dx + dy*dy (each product rounded, no contraction) for metric 0,
+ * the haversine value (monotone in the great-circle distance) for metric 1.
  */
-int64_t oracle_knn_rows(const double *locs, int64_t n, int32_t m, const int64_t *rows, int64_t nrows,
-                        int32_t *out, int32_t nthreads) {
+static double knn_key(const double *q, const double *p, int metric) {
+    if (metric == 1) return haversine(q, p);
+    const double dx = q[0] - p[0];
+    const double dy = q[1] - p[1];
+    return dx * dx + dy * dy;
+}
+
+/*
+ * The k = min(lim, m) candidates j in [0, lim) of ref nearest to q, ordered by
+ * (key, index) ascending, into out[0..m) (-1 past k).  Brute force: every j is
+ * compared with the current k-th best and inserted into a sorted list when it
+ * beats it; j ascends, so among equal keys the earlier index wins.
+ * bd and bj hold m entries.
+ */
+static void knn_one(const double *q, const double *ref, int64_t lim, int32_t m, int metric, double *bd,
+                    int32_t *bj, int32_t *out) {
+    const int32_t k = (int32_t)(lim < m ? lim : m);
+    int32_t cnt = 0;
+    for (int64_t j = 0; j < lim && k > 0; ++j) {
+        const double d = knn_key(q, ref + 2 * j, metric);
+        if (cnt == k && !(d < bd[k - 1])) continue;
+        int32_t p = (cnt == k) ? k - 1 : cnt;
+        while (p > 0 && d < bd[p - 1]) {
+            bd[p] = bd[p - 1];
+            bj[p] = bj[p - 1];
+            --p;
+        }
+        bd[p] = d;
+        bj[p] = (int32_t)j;
+        if (cnt < k) ++cnt;
+    }
+    for (int32_t t = 0; t < m; ++t) out[t] = (t < cnt) ? bj[t] : -1;
+}
+
+/*
+ * Conditioning sets by their definition (Sec. IV-B and the neighbour loop of
+ * Algorithm 1; ties and the short sets as read here): for each requested
+ * 0-based row i, the min(i, m) indices j < i closest to point i under the
+ * metric (0 Euclidean, 1 great-circle on degrees), ordered by (key, index)
+ * ascending; slots past min(i, m) are -1.  out is [nrows][m].  Returns 0, or
+ * ORACLE_EINVAL / ORACLE_ENOMEM.
+ */
+int64_t oracle_knn_rows_metric(const double *locs, int64_t n, int32_t m, int32_t metric, const int64_t *rows,
+                               int64_t nrows, int32_t *out, int32_t nthreads) {
     if (n < 0 || m < 0 || nrows < 0 || (nrows > 0 && (!rows || !out)) || (n > 0 && !locs)) return ORACLE_EINVAL;
+    if (metric != 0 && metric != 1) return ORACLE_EINVAL;
     for (int64_t r = 0; r < nrows; ++r)
         if (rows[r] < 0 || rows[r] >= n) return ORACLE_EINVAL;
     if (m == 0 || nrows == 0) return 0;
@@ -363,30 +503,164 @@ int64_t oracle_knn_rows(const double *locs, int64_t n, int32_t m, const int64_t 
         for (int64_t r = 0; r < nrows; ++r) {
             if (!bd || !bj) continue;
             const int64_t i = rows[r];
-            const int32_t k = (int32_t)(i < m ? i : m);
-            int32_t cnt = 0;
-            for (int64_t j = 0; j < i; ++j) {
-                const double dx = locs[2 * i] - locs[2 * j];
-                const double dy = locs[2 * i + 1] - locs[2 * j + 1];
-                const double d = dx * dx + dy * dy;
-                /* j ascends, so among equal distances an earlier j already wins */
-                if (cnt == k && !(d < bd[k - 1])) continue;
-                int32_t p = (cnt == k) ? k - 1 : cnt;
-                while (p > 0 && d < bd[p - 1]) {
-                    bd[p] = bd[p - 1];
-                    bj[p] = bj[p - 1];
-                    --p;
-                }
-                bd[p] = d;
-                bj[p] = (int32_t)j;
-                if (cnt < k) ++cnt;
-            }
-            for (int32_t t = 0; t < m; ++t) out[r * m + t] = (t < cnt) ? bj[t] : -1;
+            knn_one(locs + 2 * i, locs, i, m, metric, bd, bj, out + r * (int64_t)m);
         }
         free(bd);
         free(bj);
     }
     return failed ? ORACLE_ENOMEM : 0;
+}
+
+int64_t oracle_knn_rows(const double *locs, int64_t n, int32_t m, const int64_t *rows, int64_t nrows,
+                        int32_t *out, int32_t nthreads) {
+    return oracle_knn_rows_metric(locs, n, m, 0, rows, nrows, out, nthreads);
+}
+
+/*
+ * Neighbour sets of prediction points: for each query q, the min(n_ref, m)
+ * reference points nearest to it (all of them are candidates), ordered and
+ * tie-broken as above.  out is [nq][m].  Returns 0, ORACLE_EINVAL or
+ * ORACLE_ENOMEM.
+ */
+int64_t oracle_knn_query(const double *ref, int64_t n_ref, const double *q, int64_t nq, int32_t m, int32_t metric,
+                         int32_t *out, int32_t nthreads) {
+    if (n_ref < 0 || nq < 0 || m < 0 || (n_ref > 0 && !ref) || (nq > 0 && (!q || !out))) return ORACLE_EINVAL;
+    if (metric != 0 && metric != 1) return ORACLE_EINVAL;
+    if (m == 0 || nq == 0) return 0;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int failed = 0;
+#pragma omp parallel
+    {
+        double *bd = (double *)malloc((size_t)m * sizeof(double));
+        int32_t *bj = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+        if (!bd || !bj) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < nq; ++t) {
+            if (!bd || !bj) continue;
+            knn_one(q + 2 * t, ref, n_ref, m, metric, bd, bj, out + t * (int64_t)m);
+        }
+        free(bd);
+        free(bj);
+    }
+    return failed ? ORACLE_ENOMEM : 0;
+}
+
+/*
+ * Vecchia kriging (Sec. V-C): the conditional Gaussian of the observation at
+ * each prediction point given the observations at its neighbour set J
+ * (nbr row t, min(n_ref, m) valid indices into the reference points):
+ *   mean = v^T Sigma_JJ^{-1} y_J,   var = sigma2 + tau2 - v^T Sigma_JJ^{-1} v,
+ * with Sigma_JJ the covariance of the neighbours (nugget on its diagonal) and
+ * v the covariance between the neighbours and the point (no nugget).  The
+ * solve is a Cholesky factorisation and two triangular substitutions.  var is
+ * the variance of a new observation; the latent field's is var - tau2.
+ * Returns 0, ORACLE_EINVAL, ORACLE_ENOMEM, or t + 1 for the first point whose
+ * system is not positive definite or whose var is not positive (a point that
+ * coincides with a neighbour when tau2 = 0); its outputs are NaN.
+ */
+int64_t oracle_predict(const double *ref, const double *zref, int64_t n_ref, const double *q, int64_t nq,
+                       const int32_t *nbr, int32_t m, int32_t family, int32_t metric, double smooth,
+                       const double *theta, double *mean, double *var, int32_t nthreads) {
+    const cov_t cvs = {family, metric, smooth};
+    const cov_t *cv = &cvs;
+    if (n_ref < 0 || nq < 0 || m < 0 || !theta || (nq > 0 && (!q || !mean || !var))) return ORACLE_EINVAL;
+    if (n_ref > 0 && (!ref || !zref)) return ORACLE_EINVAL;
+    if (!valid_cov(cv) || !(theta[0] > 0) || !(theta[1] > 0) || !(theta[2] >= 0)) return ORACLE_EINVAL;
+    const int32_t k = (int32_t)(n_ref < m ? n_ref : m);
+    if (k > 0 && !nbr) return ORACLE_EINVAL;
+    for (int64_t t = 0; t < nq; ++t)
+        for (int32_t a = 0; a < k; ++a) {
+            const int32_t j = nbr[t * (int64_t)m + a];
+            if (j < 0 || j >= n_ref) return ORACLE_EINVAL;
+        }
+    const double sigma2 = theta[0], beta = theta[1], tau2 = theta[2];
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    int64_t first_fail = INT64_MAX;
+    int nomem = 0;
+#pragma omp parallel
+    {
+        const size_t kk = (size_t)(k > 0 ? k : 1);
+        double *L = (double *)malloc(kk * kk * sizeof(double));
+        double *v = (double *)malloc(kk * sizeof(double));
+        double *y = (double *)malloc(kk * sizeof(double));
+        double *a = (double *)malloc(kk * sizeof(double));
+        if (!L || !v || !y || !a) {
+#pragma omp atomic write
+            nomem = 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < nq; ++t) {
+            if (!L || !v || !y || !a) continue;
+            const int32_t *J = nbr + t * (int64_t)m;
+            const double *sq = q + 2 * t;
+            int bad = 0;
+            /* Sigma_JJ (lower triangle, row-major), v and y_J */
+            for (int32_t r = 0; r < k; ++r) {
+                const double *sr = ref + 2 * (int64_t)J[r];
+                for (int32_t c = 0; c <= r; ++c)
+                    L[r * k + c] = cov_fn(cv, cov_dist(cv, sr, ref + 2 * (int64_t)J[c]), sigma2, beta) +
+                                   (r == c ? tau2 : 0.0);
+                v[r] = cov_fn(cv, cov_dist(cv, sr, sq), sigma2, beta);
+                y[r] = zref[J[r]];
+            }
+            /* Cholesky in place */
+            for (int32_t r = 0; r < k && !bad; ++r) {
+                for (int32_t c = 0; c <= r; ++c) {
+                    double acc = L[r * k + c];
+                    for (int32_t p = 0; p < c; ++p) acc -= L[r * k + p] * L[c * k + p];
+                    if (r == c) {
+                        if (!(acc > 0.0) || !isfinite(acc)) {
+                            bad = 1;
+                            break;
+                        }
+                        L[r * k + r] = sqrt(acc);
+                    } else {
+                        L[r * k + c] = acc / L[c * k + c];
+                    }
+                }
+            }
+            double mu = NAN, vr = NAN;
+            if (!bad) {
+                /* a = Sigma_JJ^{-1} v: forward then back substitution */
+                for (int32_t r = 0; r < k; ++r) {
+                    double acc = v[r];
+                    for (int32_t p = 0; p < r; ++p) acc -= L[r * k + p] * a[p];
+                    a[r] = acc / L[r * k + r];
+                }
+                for (int32_t r = k - 1; r >= 0; --r) {
+                    double acc = a[r];
+                    for (int32_t p = r + 1; p < k; ++p) acc -= L[p * k + r] * a[p];
+                    a[r] = acc / L[r * k + r];
+                }
+                double my = 0.0, mv = 0.0;
+                for (int32_t r = 0; r < k; ++r) {
+                    my += a[r] * y[r];
+                    mv += a[r] * v[r];
+                }
+                mu = my;
+                vr = sigma2 + tau2 - mv;
+                if (!(vr > 0.0) || !isfinite(vr) || !isfinite(mu)) bad = 1;
+            }
+            if (bad) {
+                mu = vr = NAN;
+#pragma omp critical
+                {
+                    if (t < first_fail) first_fail = t;
+                }
+            }
+            mean[t] = mu;
+            var[t] = vr;
+        }
+        free(L);
+        free(v);
+        free(y);
+        free(a);
+    }
+    if (nomem) return ORACLE_ENOMEM;
+    return first_fail == INT64_MAX ? 0 : first_fail + 1;
 }
 
 /*
