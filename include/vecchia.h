@@ -121,6 +121,64 @@ int vecchia_loglik_terms(const double *locs, const double *z, const int32_t *nbr
                          double *gterms, int64_t *status, void *stream);
 
 /*
+ * Covariance models beyond the Matern-with-Euclidean-distance calls above.
+ *   family VECCHIA_MATERN   Eq. (2); smoothness = nu in {0.5, 1.5, 2.5}
+ *          VECCHIA_POWEXP   the power exponential of the real-data study
+ *                           (Sec. V-C), C(d) = sigma2 exp(-d^alpha / beta);
+ *                           smoothness = alpha in (0, 2]
+ *   metric VECCHIA_EUCLIDEAN     locs are (x, y)
+ *          VECCHIA_GREAT_CIRCLE  locs are (longitude, latitude) in degrees and
+ *                                d is the haversine great-circle distance in
+ *                                km on a sphere of radius 6371 km (Sec. V-C)
+ * The nugget tau2 is added to equal-index entries as for the Matern calls.
+ */
+enum vecchia_family { VECCHIA_MATERN = 0, VECCHIA_POWEXP = 1 };
+enum vecchia_metric { VECCHIA_EUCLIDEAN = 0, VECCHIA_GREAT_CIRCLE = 1 };
+
+typedef struct vecchia_cov {
+    int32_t family;
+    int32_t metric;
+    double smoothness;
+} vecchia_cov;
+
+/*
+ * vecchia_loglik / vecchia_loglik_grad under any covariance model: grad ==
+ * NULL evaluates the value only, else also dl/d(sigma2, beta, tau2) at fixed
+ * smoothness.  Arguments, workspace, status and return codes as above; an
+ * invalid model is VECCHIA_EINVAL.
+ */
+int vecchia_loglik_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                       const vecchia_cov *cov, const double *theta, double *out, double *grad, int64_t *status,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* vecchia_loglik_terms under any covariance model. */
+int vecchia_loglik_terms_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                             const vecchia_cov *cov, const double *theta, const int64_t *idx, int64_t nidx,
+                             double *terms, double *gterms, int64_t *status, void *stream);
+
+/*
+ * Vecchia kriging (the prediction of Sec. V-C): for each prediction point t
+ * the conditional mean and variance of its observation given the
+ * observations at its neighbour set (row t of nbr):
+ *   mean[t] = v^T Sigma_JJ^-1 z_J,   var[t] = sigma2 + tau2 - v^T Sigma_JJ^-1 v
+ * (the variance of a new observation; the latent field's is var - tau2).
+ *   locs, z  [dev] double[n][2], double[n]  the observed points
+ *   qlocs    [dev] double[nq][2]            prediction points
+ *   nbr      [dev] int32[nq][m]  row t: min(n, m) indices in [0, n) (any
+ *                                order, e.g. from vecchia_knn_query)
+ *   theta    [dev] double[3];  mean, var [dev] double[nq]
+ *   status   [dev] int64[1]: 0; VECCHIA_STATUS_THETA; or t + 1 for the first
+ *            point whose block is not positive definite or whose index is out
+ *            of range (a prediction point on top of a neighbour with tau2 = 0
+ *            has variance 0 and may land here); failed rows hold NaN.
+ * No workspace.  Asynchronous on the stream.  Returns VECCHIA_OK,
+ * VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED (m > VECCHIA_MAX_M) or VECCHIA_EHIP.
+ */
+int vecchia_predict(const double *locs, const double *z, int64_t n, const double *qlocs, int64_t nq,
+                    const int32_t *nbr, int32_t m, const vecchia_cov *cov, const double *theta, double *mean,
+                    double *var, int64_t *status, void *stream);
+
+/*
  * Kernel variants.  Every variant evaluates the same conditionals (Algorithm 1
  * fused per point); they differ in how a workgroup maps onto one conditional:
  *   VECCHIA_VARIANT_UNBLOCKED  256 threads, the block packed in LDS, unblocked
@@ -282,6 +340,34 @@ int vecchia_autotune(const vecchia_field *field, double nu, int32_t with_grad, c
  */
 size_t vecchia_knn_workspace_size(int64_t n);
 int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * vecchia_knn under a metric: VECCHIA_EUCLIDEAN as vecchia_knn;
+ * VECCHIA_GREAT_CIRCLE with locs as (longitude, latitude) in degrees, ranking
+ * candidates by the haversine value sin^2(dlat/2) + cos lat_i cos lat_j
+ * sin^2(dlon/2) (monotone in the great-circle distance of Sec. V-C, latitude
+ * and longitude differences taken in degrees before conversion), ties by
+ * index; every candidate is compared (O(n^2 / 2) work).  The haversine value
+ * uses the device's sine and cosine, so keys equal to the last bits may order
+ * differently from another library's.  Other arguments and returns as
+ * vecchia_knn; an unknown metric is VECCHIA_EINVAL.
+ */
+int vecchia_knn_metric(const double *locs, int64_t n, int32_t m, int32_t metric, int32_t *nbr, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/*
+ * Neighbour sets of prediction points for kriging (Sec. V-C): row t of nbr
+ * receives the min(n, m) points of locs nearest to qlocs[t] (all n points are
+ * candidates), ordered as vecchia_knn_metric orders them, -1 past min(n, m).
+ *   locs   [dev] double[n][2];  qlocs [dev] double[nq][2];  nbr [dev] int32[nq][m]
+ *   ws     [dev] at least vecchia_knn_workspace_size(n) bytes
+ * Euclidean queries use the grid of vecchia_knn over locs (queries outside
+ * its bounding box included), great-circle queries compare every point.
+ * Asynchronous.  Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED
+ * (m > VECCHIA_MAX_M), VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+int vecchia_knn_query(const double *locs, int64_t n, const double *qlocs, int64_t nq, int32_t m, int32_t metric,
+                      int32_t *nbr, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * vecchia_morton_order: the Morton (Z-order) ordering of Sec. IV-A.  Each

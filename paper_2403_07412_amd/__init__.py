@@ -126,6 +126,10 @@ def _load():
         lib.vecchia_knn_workspace_size.argtypes = [I64]
         lib.vecchia_knn.restype = ctypes.c_int
         lib.vecchia_knn.argtypes = [P, I64, I32, P, P, SZ, P]
+        lib.vecchia_knn_metric.restype = ctypes.c_int
+        lib.vecchia_knn_metric.argtypes = [P, I64, I32, I32, P, P, SZ, P]
+        lib.vecchia_knn_query.restype = ctypes.c_int
+        lib.vecchia_knn_query.argtypes = [P, I64, P, I64, I32, I32, P, P, SZ, P]
         lib.vecchia_morton_workspace_size.restype = SZ
         lib.vecchia_morton_workspace_size.argtypes = [I64]
         lib.vecchia_morton_order.restype = ctypes.c_int
@@ -142,12 +146,37 @@ def _load():
         lib.vecchia_dense_logdet_workspace_size.argtypes = [I64]
         lib.vecchia_dense_logdet.restype = ctypes.c_int
         lib.vecchia_dense_logdet.argtypes = [P, I64, I64, P, P, P, P, P, SZ, P]
+        CP = ctypes.POINTER(Cov)
+        lib.vecchia_loglik_cov.restype = ctypes.c_int
+        lib.vecchia_loglik_cov.argtypes = [P, P, P, I64, I32, CP, P, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_terms_cov.restype = ctypes.c_int
+        lib.vecchia_loglik_terms_cov.argtypes = [P, P, P, I64, I32, CP, P, P, I64, P, P, P, P]
+        lib.vecchia_predict.restype = ctypes.c_int
+        lib.vecchia_predict.argtypes = [P, P, I64, P, I64, P, I32, CP, P, P, P, P, P]
         lib.vecchia_mle.restype = ctypes.c_int
         lib.vecchia_mle.argtypes = [P, P, P, I64, I32, D, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
                                     ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
                                     ctypes.POINTER(I32), P, SZ, P]
         _lib = lib
     return _lib
+
+
+# covariance models (vecchia_cov in the C header)
+MATERN, POWEXP = 0, 1
+EUCLIDEAN, GREAT_CIRCLE = 0, 1
+
+
+class Cov(ctypes.Structure):
+    """Covariance model: family (MATERN, POWEXP), metric (EUCLIDEAN, GREAT_CIRCLE) and smoothness
+    (nu for Matern, alpha for the power exponential)."""
+    _fields_ = [("family", ctypes.c_int32), ("metric", ctypes.c_int32), ("smoothness", ctypes.c_double)]
+
+
+def _cov(cov) -> Cov:
+    if isinstance(cov, Cov):
+        return cov
+    family, metric, smoothness = cov
+    return Cov(int(family), int(metric), float(smoothness))
 
 
 def library():
@@ -255,6 +284,74 @@ def vecchia_loglik_terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_
                                       _stream(stream))
     _check(rc, "vecchia_loglik_terms")
     return terms[:nidx], (gterms[:nidx] if gterms is not None else None), status
+
+
+def vecchia_loglik_cov(locs, z, nbr, m: int, cov, theta, with_grad: bool = False, out=None, grad=None,
+                       status=None, ws=None, stream=None):
+    """Log-likelihood (and gradient) under a covariance model cov = (family, metric, smoothness);
+    returns (out[1], grad[3]|None, status[1]) without synchronising."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
+    if with_grad and grad is None:
+        grad = torch.empty(3, dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
+    _dev_check(theta, out, grad if with_grad else None, status)
+    ws = _workspace(n, m, dev, ws)
+    c = _cov(cov)
+    rc = _load().vecchia_loglik_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, ctypes.byref(c),
+                                    _ptr(theta), _ptr(out), _ptr(grad) if with_grad else None, _ptr(status),
+                                    _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_loglik_cov")
+    return out, (grad if with_grad else None), status
+
+
+def vecchia_loglik_terms_cov(locs, z, nbr, m: int, cov, theta, idx=None, with_grad: bool = False, stream=None):
+    """Per-point l_i (and gradient) under a covariance model; returns (terms, gterms|None, status)."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    if idx is not None:
+        if idx.dtype != torch.int64:
+            raise TypeError("idx must be int64")
+        _dev_check(idx)
+        nidx = idx.shape[0]
+    else:
+        nidx = n
+    terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
+    gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
+    status = torch.empty(1, dtype=torch.int64, device=dev)
+    _dev_check(theta)
+    c = _cov(cov)
+    rc = _load().vecchia_loglik_terms_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, ctypes.byref(c),
+                                          _ptr(theta), _ptr(idx), nidx, _ptr(terms), _ptr(gterms), _ptr(status),
+                                          _stream(stream))
+    _check(rc, "vecchia_loglik_terms_cov")
+    return terms[:nidx], (gterms[:nidx] if gterms is not None else None), status
+
+
+def vecchia_predict(locs, z, qlocs, nbr, m: int, cov, theta, mean=None, var=None, status=None, stream=None):
+    """Vecchia kriging: conditional mean and variance (of a new observation) at each prediction point
+    given the observations at its neighbours (row t of nbr, [nq][m] int32 indices into locs);
+    returns (mean[nq], var[nq], status[1]) without synchronising."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be float64 [n][2]")
+    if qlocs.dtype != torch.float64 or qlocs.dim() != 2 or qlocs.shape[1] != 2:
+        raise ValueError("qlocs must be float64 [nq][2]")
+    n, nq = locs.shape[0], qlocs.shape[0]
+    if z.dtype != torch.float64 or tuple(z.shape) != (n,):
+        raise ValueError("z must be float64 [n]")
+    if m > 0 and (nbr.dtype != torch.int32 or tuple(nbr.shape) != (nq, m)):
+        raise ValueError("nbr must be int32 [nq][m]")
+    dev = qlocs.device
+    mean = torch.empty(max(nq, 1), dtype=torch.float64, device=dev) if mean is None else mean
+    var = torch.empty(max(nq, 1), dtype=torch.float64, device=dev) if var is None else var
+    status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
+    _dev_check(locs, z, qlocs, nbr if m > 0 else None, theta, mean, var, status)
+    c = _cov(cov)
+    rc = _load().vecchia_predict(_ptr(locs), _ptr(z), n, _ptr(qlocs), nq, _ptr(nbr) if m > 0 else None, m,
+                                 ctypes.byref(c), _ptr(theta), _ptr(mean), _ptr(var), _ptr(status), _stream(stream))
+    _check(rc, "vecchia_predict")
+    return mean[:nq], var[:nq], status
 
 
 def _variant_id(variant) -> int:
@@ -500,9 +597,10 @@ def vecchia_knn_workspace_size(n: int) -> int:
     return int(_load().vecchia_knn_workspace_size(int(n)))
 
 
-def vecchia_knn(locs, m: int, out=None, ws=None, stream=None):
+def vecchia_knn(locs, m: int, out=None, ws=None, stream=None, metric: int = EUCLIDEAN):
     """Conditioning sets on the GPU: int32 [n][m], row i = the min(i, m) nearest points j < i by
-    (squared distance, index), -1 padded.  locs: float64 [n][2] device tensor."""
+    (key, index), -1 padded; the key is the squared distance (EUCLIDEAN) or the haversine value of
+    (longitude, latitude) degrees (GREAT_CIRCLE).  locs: float64 [n][2] device tensor."""
     if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
         raise ValueError("locs must be float64 [n][2]")
     _dev_check(locs)
@@ -515,8 +613,31 @@ def vecchia_knn(locs, m: int, out=None, ws=None, stream=None):
     need = vecchia_knn_workspace_size(n)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
-    rc = _load().vecchia_knn(_ptr(locs), n, int(m), _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
+    rc = _load().vecchia_knn_metric(_ptr(locs), n, int(m), int(metric), _ptr(out), _ptr(ws), ws.numel(),
+                                    _stream(stream))
     _check(rc, "vecchia_knn")
+    return out
+
+
+def vecchia_knn_query(locs, qlocs, m: int, metric: int = EUCLIDEAN, out=None, ws=None, stream=None):
+    """Neighbour sets of prediction points: int32 [nq][m], row t = the min(n, m) points of locs nearest
+    to qlocs[t] by (key, index), -1 padded."""
+    for t, name in ((locs, "locs"), (qlocs, "qlocs")):
+        if t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != 2:
+            raise ValueError(f"{name} must be float64 [rows][2]")
+    _dev_check(locs, qlocs)
+    n, nq = locs.shape[0], qlocs.shape[0]
+    if out is None:
+        out = torch.empty((nq, max(m, 0)), dtype=torch.int32, device=qlocs.device)
+    if tuple(out.shape) != (nq, m) or out.dtype != torch.int32:
+        raise ValueError("out must be int32 [nq][m]")
+    _dev_check(out)
+    need = vecchia_knn_workspace_size(n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=qlocs.device)
+    rc = _load().vecchia_knn_query(_ptr(locs), n, _ptr(qlocs), nq, int(m), int(metric), _ptr(out), _ptr(ws),
+                                   ws.numel(), _stream(stream))
+    _check(rc, "vecchia_knn_query")
     return out
 
 

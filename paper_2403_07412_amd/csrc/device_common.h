@@ -15,13 +15,14 @@ constexpr double kLog2Pi = 1.8378770664093454835606594728112;
 constexpr int64_t kNoFailure = INT64_MAX;     // "no failing point" sentinel in partial status words
 constexpr int kChunk = 16;                    // conditionals summed per partial (fixed: fixes the summation order)
 
-// Covariance parameters as the kernels use them.
+// Covariance parameters as the kernels use them; alpha is the exponent of
+// the power exponential (unused by the Matern codes).
 struct Params {
-    double sigma2, beta, tau2, inv_beta;
+    double sigma2, beta, tau2, inv_beta, alpha;
     bool valid;
 };
 
-__device__ inline Params load_params(const double *__restrict__ theta) {
+__device__ inline Params load_params(const double *__restrict__ theta, double alpha = 1.0) {
     Params p;
     p.sigma2 = theta[0];
     p.beta = theta[1];
@@ -29,7 +30,40 @@ __device__ inline Params load_params(const double *__restrict__ theta) {
     p.valid = (p.sigma2 > 0.0) && (p.beta > 0.0) && (p.tau2 >= 0.0) && isfinite(p.sigma2) && isfinite(p.beta) &&
               isfinite(p.tau2);
     p.inv_beta = 1.0 / p.beta;
+    p.alpha = alpha;
     return p;
+}
+
+// Covariance codes of the kernels: KC = family + 4 * metric, family 0, 1, 2
+// for Matern nu = 1/2, 3/2, 5/2 (Eq. (2)) and 3 for the power exponential
+// sigma2 exp(-d^alpha / beta) (Sec. V-C); metric 0 Euclidean on (x, y), 1
+// great-circle on (longitude, latitude) in degrees, in kilometres.
+__host__ __device__ constexpr int kc_family(int KC) { return KC & 3; }
+__host__ __device__ constexpr bool kc_gcd(int KC) { return (KC >> 2) != 0; }
+constexpr double kEarthRadiusKm = 6371.0;
+constexpr double kDeg2Rad = 0.017453292519943295769236907684886;
+
+// Great-circle distance in km between (lon, lat) points a and b in degrees,
+// given cos(lat) of each: hav(d / R) = hav(dlat) + cos lat_a cos lat_b hav(dlon)
+// with hav(t) = sin^2(t / 2), differences taken in degrees first.  Coincident
+// points give exactly 0.
+__device__ __forceinline__ double gcd_km(double lona, double lata, double ca, double lonb, double latb, double cb) {
+    const double s1 = sin(0.5 * ((lata - latb) * kDeg2Rad));
+    const double s2 = sin(0.5 * ((lona - lonb) * kDeg2Rad));
+    const double h = fmin(fma(s1, s1, (ca * cb) * (s2 * s2)), 1.0);
+    return (2.0 * kEarthRadiusKm) * asin(sqrt(h));
+}
+
+// Scaled distance r fed to the closed forms: d / beta (Matern) or
+// d^alpha / beta (power exponential; alpha = 1 and 2 without pow).
+template <int KC>
+__device__ __forceinline__ double cov_scaled(double d, const Params &P) {
+    if constexpr (kc_family(KC) == 3) {
+        const double da = (P.alpha == 1.0) ? d : (P.alpha == 2.0) ? d * d : pow(d, P.alpha);
+        return da * P.inv_beta;
+    } else {
+        return d * P.inv_beta;
+    }
 }
 
 // e^{-r} for r >= 0.  Range reduction x = -r = k ln2 + f with |f| <= ln2/2
@@ -117,19 +151,28 @@ __device__ __forceinline__ double sqrt_pos(double s) {
     return fma(d, h, g);
 }
 
-// Matern covariance sigma2 * m(r) and, with WITH_D, its beta-derivative
-// sigma2 h(r) / beta (h as in matern_dbeta_r) for points a and b, using
-// exp_neg_tab.  The coordinates must be finite.
-template <int NU, bool WITH_D>
-__device__ __forceinline__ void matern_pair(double xa, double ya, double xb, double yb, const Params &P, double s2b,
-                                            const double *tab, double &c, double &db) {
-    const double dx = xa - xb, dy = ya - yb;
-    const double r = sqrt_pos(fma(dx, dx, dy * dy)) * P.inv_beta;
+// Covariance C(d) and, with WITH_D, its beta-derivative for points a and b
+// (cos of the latitudes in ca, cb for the great-circle codes), using
+// exp_neg_tab.  With r the scaled distance, the Matern forms are sigma2 m(r)
+// and sigma2 h(r) / beta (h as in matern_dbeta_r); the power exponential is
+// sigma2 e^-r with derivative sigma2 r e^-r / beta, the nu = 1/2 form.  The
+// coordinates must be finite.
+template <int KC, bool WITH_D>
+__device__ __forceinline__ void cov_pair(double xa, double ya, double ca, double xb, double yb, double cb,
+                                         const Params &P, double s2b, const double *tab, double &c, double &db) {
+    double r;
+    if constexpr (kc_gcd(KC)) {
+        r = cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P);
+    } else {
+        const double dx = xa - xb, dy = ya - yb;
+        r = cov_scaled<KC>(sqrt_pos(fma(dx, dx, dy * dy)), P);
+    }
     const double e = exp_neg_tab(r, tab);
-    if constexpr (NU == 0) {
+    constexpr int F = kc_family(KC);
+    if constexpr (F == 0 || F == 3) {
         c = P.sigma2 * e;
         if constexpr (WITH_D) db = s2b * (r * e);
-    } else if constexpr (NU == 1) {
+    } else if constexpr (F == 1) {
         c = P.sigma2 * ((1.0 + r) * e);
         if constexpr (WITH_D) db = s2b * ((r * r) * e);
     } else {
@@ -138,12 +181,14 @@ __device__ __forceinline__ void matern_pair(double xa, double ya, double xb, dou
     }
 }
 
-// Matern covariance, Eq. (2), for half-integer smoothness in closed form.
-// NU: 0 -> nu = 0.5, 1 -> nu = 1.5, 2 -> nu = 2.5.  r = distance / beta.
+// Closed forms in the scaled distance r: Matern, Eq. (2), for half-integer
+// smoothness (NU: 0 -> nu = 0.5, 1 -> nu = 1.5, 2 -> nu = 2.5, r = d / beta)
+// and the power exponential (NU = 3, r = d^alpha / beta), whose form is the
+// nu = 1/2 one.
 template <int NU>
 __device__ __forceinline__ double matern_r(double r, double sigma2) {
     double e = exp_neg(r);
-    if constexpr (NU == 0) {
+    if constexpr (NU == 0 || NU == 3) {
         return sigma2 * e;
     } else if constexpr (NU == 1) {
         return sigma2 * ((1.0 + r) * e);
@@ -157,7 +202,7 @@ __device__ __forceinline__ double matern_r(double r, double sigma2) {
 template <int NU>
 __device__ __forceinline__ double matern_dbeta_r(double r, double sigma2_over_beta) {
     double e = exp_neg(r);
-    if constexpr (NU == 0) {
+    if constexpr (NU == 0 || NU == 3) {
         return sigma2_over_beta * (r * e);
     } else if constexpr (NU == 1) {
         return sigma2_over_beta * ((r * r) * e);
@@ -171,7 +216,7 @@ template <int NU>
 __device__ __forceinline__ void matern_and_dbeta_r(double r, double sigma2, double sigma2_over_beta, double &c,
                                                    double &db) {
     double e = exp_neg(r);
-    if constexpr (NU == 0) {
+    if constexpr (NU == 0 || NU == 3) {
         c = sigma2 * e;
         db = sigma2_over_beta * (r * e);
     } else if constexpr (NU == 1) {
@@ -187,6 +232,17 @@ __device__ __forceinline__ double dist2d(double ax, double ay, double bx, double
     double dx = ax - bx;
     double dy = ay - by;
     return sqrt_dist(fma(dx, dx, dy * dy));
+}
+
+// Scaled distance of a pair under covariance code KC (the unblocked kernel's form).
+template <int KC>
+__device__ __forceinline__ double cov_r(double xa, double ya, double ca, double xb, double yb, double cb,
+                                        const Params &P) {
+    if constexpr (kc_gcd(KC)) {
+        return cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P);
+    } else {
+        return cov_scaled<KC>(dist2d(xa, ya, xb, yb), P);
+    }
 }
 
 // Sum over the 64 lanes of a wavefront; fixed butterfly order, every lane gets the total.

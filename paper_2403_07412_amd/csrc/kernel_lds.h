@@ -28,8 +28,11 @@
 
 namespace vecchia {
 
+// Per-conditional results.  mean and var are the conditional mean and
+// variance of the point's observation given its set (mu_i and c_i; with the
+// point's own observation taken as 0 they are the kriging prediction).
 struct CondOut {
-    double ell, g0, g1, g2;
+    double ell, g0, g1, g2, mean, var;
     bool bad;
 };
 
@@ -38,17 +41,23 @@ __host__ __device__ constexpr int64_t tri(int64_t a) { return a * (a + 1) / 2; }
 // LDS bytes the unblocked kernel needs for conditioning sets of up to m points.
 __host__ __device__ inline size_t lds_kernel_smem_bytes(int m) {
     int64_t rows = (int64_t)m + 2;
-    return (size_t)(tri(rows) + 5 * (int64_t)(m + 2) + 16) * sizeof(double);
+    return (size_t)(tri(rows) + 6 * (int64_t)(m + 2) + 16) * sizeof(double);
 }
 
-template <int NU, bool GRAD>
+// One conditional.  Likelihood mode (qloc == NULL): point i of the n points,
+// k = min(i, m) neighbours, all with indices below i.  Prediction mode: the
+// point is the location qloc with observation 0, k = min(n, m) neighbours
+// with indices below n, row i of nbr.
+template <int KC, bool GRAD>
 __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ locs, const double *__restrict__ z,
-                                   const int32_t *__restrict__ nbr, int64_t i, int32_t m, const Params &P,
-                                   double *smem) {
+                                   const int32_t *__restrict__ nbr, int64_t i, int64_t n, int32_t m,
+                                   const double *qloc, const Params &P, double *smem) {
     constexpr int NT = 256;
+    constexpr int F = kc_family(KC);
     const int tid = threadIdx.x;
     const int lane = tid % kWave, wave = tid / kWave;
-    const int k = (int)(i < m ? i : m);
+    const int64_t lim = qloc ? n : i;
+    const int k = (int)(lim < m ? lim : m);
     const int rows = k + 2;  // rows 0..k+1
     double *A = smem;
     double *X = A + tri(m + 2);
@@ -56,7 +65,8 @@ __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ lo
     double *Zv = Y + (m + 2);
     double *Q1 = Zv + (m + 2);
     double *Q2 = Q1 + (m + 2);
-    double *red = Q2 + (m + 2);  // reduction scratch
+    double *CL = Q2 + (m + 2);   // cos(latitude), great-circle codes
+    double *red = CL + (m + 2);  // reduction scratch
     bool mybad = false;
 
     __syncthreads();  // the previous conditional is done with smem
@@ -65,13 +75,16 @@ __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ lo
         int64_t j = i;
         if (t < k) {
             const int32_t jj = nbr[i * (int64_t)m + t];
-            const bool okj = (jj >= 0) && ((int64_t)jj < i);
+            const bool okj = (jj >= 0) && ((int64_t)jj < lim);
             mybad |= !okj;
             j = okj ? (int64_t)jj : 0;
         }
-        X[t] = locs[2 * j];
-        Y[t] = locs[2 * j + 1];
-        Zv[t] = z[j];
+        const bool self = t == k && qloc;
+        X[t] = self ? qloc[0] : locs[2 * j];
+        Y[t] = self ? qloc[1] : locs[2 * j + 1];
+        Zv[t] = self ? 0.0 : z[j];
+        if constexpr (kc_gcd(KC)) CL[t] = cos(Y[t] * kDeg2Rad);
+        mybad |= !(isfinite(X[t]) && isfinite(Y[t]) && isfinite(Zv[t]));
     }
     __syncthreads();
 
@@ -79,10 +92,10 @@ __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ lo
     for (int a = wave; a <= k + 1; a += NT / kWave) {
         double *row = A + tri(a);
         if (a <= k) {
-            const double xa = X[a], ya = Y[a];
+            const double xa = X[a], ya = Y[a], ca = kc_gcd(KC) ? CL[a] : 0.0;
             for (int b = lane; b <= a; b += kWave) {
-                const double r = dist2d(xa, ya, X[b], Y[b]) * P.inv_beta;
-                const double c = matern_r<NU>(r, P.sigma2);
+                const double r = cov_r<KC>(xa, ya, ca, X[b], Y[b], kc_gcd(KC) ? CL[b] : 0.0, P);
+                const double c = matern_r<F>(r, P.sigma2);
                 row[b] = (a == b) ? c + P.tau2 : c;
             }
         } else {
@@ -112,6 +125,8 @@ __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ lo
     const double w = A[tri(k + 1) + k];
     o.ell = -0.5 * (kLog2Pi + 2.0 * log(Lkk) + w * w);
     o.g0 = o.g1 = o.g2 = 0.0;
+    o.var = Lkk * Lkk;
+    o.mean = Zv[k] - w * Lkk;
 
     if constexpr (GRAD) {
         const double c = Lkk * Lkk;
@@ -147,10 +162,10 @@ __device__ __forceinline__ CondOut lds_conditional(const double *__restrict__ lo
         double gb = 0.0;
         const double s2b = P.sigma2 * P.inv_beta;
         for (int a = wave + 1; a <= k; a += NT / kWave) {
-            const double xa = X[a], ya = Y[a], ua = U[a], ba = Bv[a];
+            const double xa = X[a], ya = Y[a], ua = U[a], ba = Bv[a], ca = kc_gcd(KC) ? CL[a] : 0.0;
             for (int b = lane; b < a; b += kWave) {
-                const double r = dist2d(xa, ya, X[b], Y[b]) * P.inv_beta;
-                gb += matern_dbeta_r<NU>(r, s2b) * (ua * Bv[b] + U[b] * ba);
+                const double r = cov_r<KC>(xa, ya, ca, X[b], Y[b], kc_gcd(KC) ? CL[b] : 0.0, P);
+                gb += matern_dbeta_r<F>(r, s2b) * (ua * Bv[b] + U[b] * ba);
             }
         }
         ub = block_sum<NT / kWave>(ub, red);

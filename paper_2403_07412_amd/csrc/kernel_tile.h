@@ -54,8 +54,8 @@ __host__ __device__ constexpr int tile_extra_vgprs(int T, int W) {
     return ((T == 5 && W == 4) || (T == 7 && W == 8)) ? 64 : 0;
 }
 
-__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d) {
-    const int lds = (2 * T * 256 + 272 + 8 * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds<T>::BYTES
+__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool gcd = false) {
+    const int lds = (2 * T * 256 + 272 + (gcd ? 9 : 8) * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds::BYTES
     const int blocks_lds = 163840 / lds;
     const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 96 + tile_extra_vgprs(T, W);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
@@ -71,12 +71,13 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d)
 // Whether the gradient keeps the beta-derivative tiles in registers (one
 // exponential per entry) or recomputes them after the solves: kept only when
 // the extra registers cost no occupancy.
-__host__ __device__ constexpr bool keep_dbeta(int T, int W) {
-    return VECCHIA_KEEP_DBETA && tile_waves_per_simd(T, W, true) >= tile_waves_per_simd(T, W, false);
+__host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
+    return VECCHIA_KEEP_DBETA && tile_waves_per_simd(T, W, true, gcd) >= tile_waves_per_simd(T, W, false, gcd);
 }
 
-// LDS layout of the tiled kernel, in doubles.
-template <int T>
+// LDS layout of the tiled kernel, in doubles.  The great-circle codes add
+// cos(latitude) of every row at the end; the other offsets do not depend on it.
+template <int T, bool GCD = false>
 struct TileLds {
     static constexpr int KP = 16 * T;
     static constexpr int LINV = 0;                  // [T][64 lanes][4]   inverse diagonal tiles, T-layout
@@ -90,9 +91,11 @@ struct TileLds {
     static constexpr int SCAL = UB + 2 * KP;        // [16]               scalars: [0] L_kk
     static constexpr int RED = SCAL + 16;           // [2][32]            reductions (two values, up to 8 waves x 4 rows)
     static constexpr int EXPT = RED + 64;           // [64][2]            2^(j/64) as hi, lo for exp_neg_tab
-    static constexpr int TOTAL = EXPT + 2 * kExpTableSize;
+    static constexpr int CL = EXPT + 2 * kExpTableSize;  // [KP]         cos(latitude) (great-circle codes only)
+    static constexpr int TOTAL = CL + (GCD ? KP : 0);
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
-    static_assert(TOTAL == 2 * T * 256 + 272 + 8 * KP + 80 + 2 * kExpTableSize, "occupancy estimate out of date");
+    static_assert(TOTAL == 2 * T * 256 + 272 + (GCD ? 9 : 8) * KP + 80 + 2 * kExpTableSize,
+                  "occupancy estimate out of date");
 };
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -340,11 +343,14 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
     __builtin_amdgcn_s_setprio(0);
 }
 
-template <int T, int W, int NU, bool GRAD>
+// One conditional (modes as lds_conditional: qloc == NULL for the
+// likelihood term of point i, else the prediction at qloc from row i of nbr).
+template <int T, int W, int KC, bool GRAD>
 __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ locs, const double *__restrict__ z,
-                                    const int32_t *__restrict__ nbr, int64_t i, int32_t m, const Params &P,
-                                    double *smem) {
-    using Ls = TileLds<T>;
+                                    const int32_t *__restrict__ nbr, int64_t i, int64_t n, int32_t m,
+                                    const double *qloc, const Params &P, double *smem) {
+    constexpr bool GCD = kc_gcd(KC);
+    using Ls = TileLds<T, GCD>;
     constexpr int NT = W * kWave;
     constexpr int NTW = tiles_per_wave(T, W);
     constexpr int NTILES = tile_count(T);
@@ -353,9 +359,11 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int l = tid % kWave;
     const int g = l / 16, j = l % 16;
-    const int k = (int)(i < m ? i : m);
+    const int64_t lim = qloc ? n : i;
+    const int k = (int)(lim < m ? lim : m);
     double *XY = smem + Ls::XY;
     double *Z = smem + Ls::ZV;
+    double *CLv = smem + Ls::CL;
     bool bad = false;
 
     // my tiles: slot s holds tile index w + W s; (R, C) packed as R * 32 + C, -1 if unused
@@ -380,19 +388,25 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             int64_t jj = i;
             if (t < k) {
                 const int32_t jn = nbr[i * (int64_t)m + t];
-                const bool okj = (jn >= 0) && ((int64_t)jn < i);
+                const bool okj = (jn >= 0) && ((int64_t)jn < lim);
                 bad |= !okj;
                 jj = okj ? (int64_t)jn : 0;
             }
-            const double2 p = *reinterpret_cast<const double2 *>(locs + 2 * jj);
-            x = p.x;
-            y = p.y;
-            zz = z[jj];
+            if (t == k && qloc) {  // prediction point, observation taken as 0
+                x = qloc[0];
+                y = qloc[1];
+            } else {
+                const double2 p = *reinterpret_cast<const double2 *>(locs + 2 * jj);
+                x = p.x;
+                y = p.y;
+                zz = z[jj];
+            }
             bad |= !(isfinite(x) && isfinite(y) && isfinite(zz));
         }
         XY[2 * t] = x;
         XY[2 * t + 1] = y;
         Z[t] = zz;
+        if constexpr (GCD) CLv[t] = cos(y * kDeg2Rad);
     }
     if (tid < kExpTableSize) {
         smem[Ls::EXPT + 2 * tid] = kExp2Frac64[tid].hi;
@@ -405,7 +419,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     // and diagonal tiles (the nugget) need per-entry cases; the branches on
     // them are uniform over the wavefront.  With the gradient, dC/dbeta is
     // kept in dtile from the same exponential when registers allow.
-    constexpr bool KEEP_D = GRAD && keep_dbeta(T, W);
+    constexpr bool KEEP_D = GRAD && keep_dbeta(T, W, GCD);
     const double *ET = smem + Ls::EXPT;
     dvec4 tile[NTW];
     dvec4 dtile[KEEP_D ? NTW : 1];
@@ -417,12 +431,12 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const int R_ = SR(s), C_ = SC(s);
         if (R_ < 0) continue;
         const int a = 16 * R_ + j;
-        const double xa = XY[2 * a], ya = XY[2 * a + 1];
+        const double xa = XY[2 * a], ya = XY[2 * a + 1], ca = GCD ? CLv[a] : 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int b = 16 * C_ + 4 * r + g;
             double cv, db;
-            matern_pair<NU, KEEP_D>(xa, ya, XY[2 * b], XY[2 * b + 1], P, s2b, ET, cv, db);
+            cov_pair<KC, KEEP_D>(xa, ya, ca, XY[2 * b], XY[2 * b + 1], GCD ? CLv[b] : 0.0, P, s2b, ET, cv, db);
             tile[s][r] = cv;
             if constexpr (KEEP_D) dtile[s][r] = db;
         }
@@ -511,6 +525,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     const double wv = smem[Ls::YP + k];
     o.ell = -0.5 * (kLog2Pi + 2.0 * log(Lkk) + wv * wv);
     o.g0 = o.g1 = o.g2 = 0.0;
+    o.var = Lkk * Lkk;
+    o.mean = Z[k] - wv * Lkk;
 
     if constexpr (GRAD) {
         const double c = Lkk * Lkk;
@@ -578,12 +594,13 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             if constexpr (KEEP_D) {
                 db4 = dtile[s];
             } else {
-                const double xa = XY[2 * a], ya = XY[2 * a + 1];
+                const double xa = XY[2 * a], ya = XY[2 * a + 1], ca = GCD ? CLv[a] : 0.0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int b = 16 * C_ + 4 * r + g;
                     double cv, db;
-                    matern_pair<NU, true>(xa, ya, XY[2 * b], XY[2 * b + 1], P, s2b, ET, cv, db);
+                    cov_pair<KC, true>(xa, ya, ca, XY[2 * b], XY[2 * b + 1], GCD ? CLv[b] : 0.0, P, s2b, ET, cv,
+                                       db);
                     db4[r] = db;
                 }
             }

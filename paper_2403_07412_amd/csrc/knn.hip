@@ -1,5 +1,6 @@
 // Preprocessing on the GPU: the m nearest previously ordered neighbours of
-// every point (the conditioning sets J_i of Eq. (7), Sec. IV-B) and the
+// every point (the conditioning sets J_i of Eq. (7), Sec. IV-B), the m
+// nearest observed points of prediction points (kriging, Sec. V-C) and the
 // Morton ordering (Sec. IV-A).
 //
 // Neighbour search: points are binned into a uniform grid over their bounding
@@ -12,6 +13,9 @@
 // it fills.  Early points (i below kBruteMax) scan all j < i instead.  The
 // result is exactly the brute-force answer: the order (squared distance,
 // index) is total and every candidate that could beat the m-th best is seen.
+// Prediction points search all observed points the same way.  Great-circle
+// sets (points as (longitude, latitude) in degrees) rank candidates by the
+// haversine value and scan every candidate.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
@@ -38,6 +42,19 @@ __device__ __forceinline__ double sqdist(double ax, double ay, double bx, double
     const double dx = ax - bx;
     const double dy = ay - by;
     return dx * dx + dy * dy;
+}
+#pragma clang fp contract(on)
+
+constexpr double kDeg2Rad = 0.017453292519943295769236907684886;
+
+// haversine value sin^2(dlat/2) + cos lat_q cos lat_p sin^2(dlon/2), clamped
+// to 1, differences in degrees first: monotone in the great-circle distance
+#pragma clang fp contract(off)
+__device__ __forceinline__ double hav_key(double lonq, double latq, double cq, double lonp, double latp, double cp) {
+    const double s1 = sin(0.5 * ((latq - latp) * kDeg2Rad));
+    const double s2 = sin(0.5 * ((lonq - lonp) * kDeg2Rad));
+    const double h = s1 * s1 + (cq * cp) * (s2 * s2);
+    return h > 1.0 ? 1.0 : h;
 }
 #pragma clang fp contract(on)
 
@@ -246,28 +263,33 @@ __device__ __forceinline__ void ring_cell(int r, int e, int &dx, int &dy) {
     }
 }
 
+// Query i (0 <= i < nq): its candidates are the points j < lim of locs, with
+// lim = i for conditioning sets (qlocs == NULL, query point locs[i]) and
+// lim = n for prediction points (query point qlocs[i]).
 __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
-    const double *__restrict__ locs, int64_t n, int32_t m, const double2 *__restrict__ sxy,
-    const int32_t *__restrict__ sidx, const int32_t *__restrict__ cstart, const GridParams *__restrict__ gp, int g,
-    int32_t *__restrict__ nbr) {
+    const double *__restrict__ locs, int64_t n, const double *__restrict__ qlocs, int64_t nq, int32_t m,
+    const double2 *__restrict__ sxy, const int32_t *__restrict__ sidx, const int32_t *__restrict__ cstart,
+    const GridParams *__restrict__ gp, int g, int32_t *__restrict__ nbr) {
     __shared__ double sbd[kKnnWaves][kKnnCap];
     __shared__ int32_t sbj[kKnnWaves][kKnnCap];
     const int w = threadIdx.x / kWaveK, lane = threadIdx.x % kWaveK;
     const int64_t i = blockIdx.x * (int64_t)kKnnWaves + w;
-    if (i >= n) return;  // whole wavefront; the kernel has no workgroup barrier
-    const int k = (int)(i < m ? i : m);
+    if (i >= nq) return;  // whole wavefront; the kernel has no workgroup barrier
+    const int64_t lim = qlocs ? n : i;
+    const int k = (int)(lim < m ? lim : m);
     int32_t *out = nbr + i * (int64_t)m;
     if (k == 0) {
         for (int t = lane; t < m; t += kWaveK) out[t] = -1;
         return;
     }
-    const double qx = locs[2 * i], qy = locs[2 * i + 1];
+    const double *qp = qlocs ? qlocs + 2 * i : locs + 2 * i;
+    const double qx = qp[0], qy = qp[1];
     TopK top{sbd[w], sbj[w], 0, k, lane, INFINITY, INT32_MAX};
 
-    if (i <= kBruteMax) {
-        for (int64_t base = 0; base < i; base += kWaveK) {
+    if (lim <= kBruteMax) {
+        for (int64_t base = 0; base < lim; base += kWaveK) {
             const int64_t j = base + lane;
-            const bool valid = j < i;
+            const bool valid = j < lim;
             const double d = valid ? sqdist(qx, qy, locs[2 * j], locs[2 * j + 1]) : 0.0;
             top.consider(valid, d, (int32_t)j);
         }
@@ -285,9 +307,9 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
                 const bool inside = e < ncell && X >= 0 && X < g && Y >= 0 && Y < g;
                 int32_t pp = inside ? cstart[Y * g + X] : 0;
                 const int32_t pe = inside ? cstart[Y * g + X + 1] : 0;
-                // walk each lane's cell while its points precede i
+                // walk each lane's cell while its points precede lim
                 for (;;) {
-                    const bool active = pp < pe && sidx[pp] < i;
+                    const bool active = pp < pe && sidx[pp] < lim;
                     if (__ballot(active) == 0) break;
                     double d = 0.0;
                     int32_t j = 0;
@@ -311,6 +333,42 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
                 if (dmin > 0.0 && dmin * dmin > top.thr_d) break;
             }
         }
+    }
+    top.trim();
+    for (int t = lane; t < m; t += kWaveK) out[t] = (t < top.c) ? top.bj[t] : -1;
+}
+
+__global__ void cos_lat_kernel(const double *__restrict__ locs, int64_t n, double *__restrict__ clat) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) clat[i] = cos(locs[2 * i + 1] * kDeg2Rad);
+}
+
+// Great-circle sets by brute force: query i against every candidate j < lim
+// (lim as in knn_query_kernel), keys from hav_key with clat[j] = cos(lat_j).
+__global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_gcd_kernel(
+    const double *__restrict__ locs, const double *__restrict__ clat, int64_t n, const double *__restrict__ qlocs,
+    int64_t nq, int32_t m, int32_t *__restrict__ nbr) {
+    __shared__ double sbd[kKnnWaves][kKnnCap];
+    __shared__ int32_t sbj[kKnnWaves][kKnnCap];
+    const int w = threadIdx.x / kWaveK, lane = threadIdx.x % kWaveK;
+    const int64_t i = blockIdx.x * (int64_t)kKnnWaves + w;
+    if (i >= nq) return;
+    const int64_t lim = qlocs ? n : i;
+    const int k = (int)(lim < m ? lim : m);
+    int32_t *out = nbr + i * (int64_t)m;
+    if (k == 0) {
+        for (int t = lane; t < m; t += kWaveK) out[t] = -1;
+        return;
+    }
+    const double *qp = qlocs ? qlocs + 2 * i : locs + 2 * i;
+    const double qlon = qp[0], qlat = qp[1];
+    const double cq = qlocs ? cos(qlat * kDeg2Rad) : clat[i];
+    TopK top{sbd[w], sbj[w], 0, k, lane, INFINITY, INT32_MAX};
+    for (int64_t base = 0; base < lim; base += kWaveK) {
+        const int64_t j = base + lane;
+        const bool valid = j < lim;
+        const double d = valid ? hav_key(qlon, qlat, cq, locs[2 * j], locs[2 * j + 1], clat[j]) : 0.0;
+        top.consider(valid, d, (int32_t)j);
     }
     top.trim();
     for (int t = lane; t < m; t += kWaveK) out[t] = (t < top.c) ? top.bj[t] : -1;
@@ -359,7 +417,7 @@ __global__ void widen_kernel(const int32_t *__restrict__ v, int64_t n, int64_t *
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct KnnLayout {
-    size_t part, params, key, val, skey, sval, count, cstart, sxy, temp, total, temp_bytes;
+    size_t part, params, key, val, skey, sval, count, cstart, sxy, clat, temp, total, temp_bytes;
     int g;
     int64_t cells;
 };
@@ -388,6 +446,7 @@ KnnLayout knn_layout(int64_t n) {
     L.count = o;  o += align256(sizeof(int32_t) * (size_t)(L.cells + 1));
     L.cstart = o; o += align256(sizeof(int32_t) * (size_t)(L.cells + 1));
     L.sxy = o;    o += align256(sizeof(double2) * nn);
+    L.clat = o;   o += align256(sizeof(double) * nn);
     L.temp_bytes = knn_temp_bytes((int64_t)nn, L.cells);
     L.temp = o;   o += align256(L.temp_bytes);
     L.total = o;
@@ -429,16 +488,22 @@ int blocks_for(int64_t count, int threads) { return (int)((count + threads - 1) 
 
 extern "C" size_t vecchia_knn_workspace_size(int64_t n) { return knn_layout(n < 0 ? 0 : n).total; }
 
-extern "C" int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws, size_t ws_bytes,
-                           void *stream) {
-    if (n < 0 || m < 0 || n > INT32_MAX) return VECCHIA_EINVAL;
-    if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
-    if (n == 0 || m == 0) return VECCHIA_OK;
-    if (!locs || !nbr) return VECCHIA_EINVAL;
+namespace {
+
+// Sets of nq queries against the n points of locs (self sets when qlocs is
+// NULL, then nq = n).  The grid over locs serves the Euclidean metric.
+int knn_run(const double *locs, int64_t n, const double *qlocs, int64_t nq, int32_t m, int32_t metric, int32_t *nbr,
+            void *ws, size_t ws_bytes, hipStream_t s) {
     const KnnLayout L = knn_layout(n);
     if (!ws || ws_bytes < L.total) return VECCHIA_EWORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
+    if (metric == VECCHIA_GREAT_CIRCLE) {
+        double *clat = (double *)(base + L.clat);
+        if (n > 0) hipLaunchKernelGGL(cos_lat_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, clat);
+        hipLaunchKernelGGL(knn_gcd_kernel, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s, locs,
+                           (const double *)clat, n, qlocs, nq, m, nbr);
+        return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+    }
     double *part = (double *)(base + L.part);
     GridParams *gp = (GridParams *)(base + L.params);
     int32_t *key = (int32_t *)(base + L.key), *val = (int32_t *)(base + L.val);
@@ -446,25 +511,54 @@ extern "C" int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nb
     int32_t *count = (int32_t *)(base + L.count), *cstart = (int32_t *)(base + L.cstart);
     double2 *sxy = (double2 *)(base + L.sxy);
     void *temp = base + L.temp;
-
-    hipLaunchKernelGGL(box_partial_kernel, dim3(kBoxBlocks), dim3(256), 0, s, locs, n, part);
-    hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(kBoxBlocks), 0, s, part, L.g, gp);
-    hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(blocks_for(L.cells + 1, 256), 4096)), dim3(256), 0, s, count,
-                       L.cells + 1, 0);
-    hipLaunchKernelGGL(cell_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, gp, L.g, key, val, count);
-    if (hipGetLastError() != hipSuccess) return VECCHIA_EHIP;
-    size_t tb = L.temp_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(temp, tb, key, skey, val, sval, (int)n, 0, bits_for(L.cells), s) !=
-        hipSuccess)
-        return VECCHIA_EHIP;
-    tb = L.temp_bytes;
-    if (hipcub::DeviceScan::ExclusiveSum(temp, tb, count, cstart, (int)(L.cells + 1), s) != hipSuccess)
-        return VECCHIA_EHIP;
-    hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, sval, sxy);
-    hipLaunchKernelGGL(knn_query_kernel, dim3(blocks_for(n, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s, locs, n, m,
-                       (const double2 *)sxy, (const int32_t *)sval, (const int32_t *)cstart, (const GridParams *)gp,
-                       L.g, nbr);
+    if (n > 0) {
+        hipLaunchKernelGGL(box_partial_kernel, dim3(kBoxBlocks), dim3(256), 0, s, locs, n, part);
+        hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(kBoxBlocks), 0, s, part, L.g, gp);
+        hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(blocks_for(L.cells + 1, 256), 4096)), dim3(256), 0, s,
+                           count, L.cells + 1, 0);
+        hipLaunchKernelGGL(cell_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, gp, L.g, key, val,
+                           count);
+        if (hipGetLastError() != hipSuccess) return VECCHIA_EHIP;
+        size_t tb = L.temp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(temp, tb, key, skey, val, sval, (int)n, 0, bits_for(L.cells), s) !=
+            hipSuccess)
+            return VECCHIA_EHIP;
+        tb = L.temp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, count, cstart, (int)(L.cells + 1), s) != hipSuccess)
+            return VECCHIA_EHIP;
+        hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, sval, sxy);
+    }
+    hipLaunchKernelGGL(knn_query_kernel, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s, locs, n,
+                       qlocs, nq, m, (const double2 *)sxy, (const int32_t *)sval, (const int32_t *)cstart,
+                       (const GridParams *)gp, L.g, nbr);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+}
+
+}  // namespace
+
+extern "C" int vecchia_knn_metric(const double *locs, int64_t n, int32_t m, int32_t metric, int32_t *nbr, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    if (n < 0 || m < 0 || n > INT32_MAX) return VECCHIA_EINVAL;
+    if (metric != VECCHIA_EUCLIDEAN && metric != VECCHIA_GREAT_CIRCLE) return VECCHIA_EINVAL;
+    if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
+    if (n == 0 || m == 0) return VECCHIA_OK;
+    if (!locs || !nbr) return VECCHIA_EINVAL;
+    return knn_run(locs, n, nullptr, n, m, metric, nbr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws, size_t ws_bytes,
+                           void *stream) {
+    return vecchia_knn_metric(locs, n, m, VECCHIA_EUCLIDEAN, nbr, ws, ws_bytes, stream);
+}
+
+extern "C" int vecchia_knn_query(const double *locs, int64_t n, const double *qlocs, int64_t nq, int32_t m,
+                                 int32_t metric, int32_t *nbr, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 0 || nq < 0 || m < 0 || n > INT32_MAX || nq > INT32_MAX) return VECCHIA_EINVAL;
+    if (metric != VECCHIA_EUCLIDEAN && metric != VECCHIA_GREAT_CIRCLE) return VECCHIA_EINVAL;
+    if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
+    if (nq == 0 || m == 0) return VECCHIA_OK;
+    if (!qlocs || !nbr || (n > 0 && !locs)) return VECCHIA_EINVAL;
+    return knn_run(locs, n, qlocs, nq, m, metric, nbr, ws, ws_bytes, (hipStream_t)stream);
 }
 
 extern "C" size_t vecchia_morton_workspace_size(int64_t n) { return morton_layout(n < 0 ? 0 : n).total; }

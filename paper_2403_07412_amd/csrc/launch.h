@@ -1,7 +1,8 @@
 // Launch machinery shared by the kernel translation units: the per-point
 // conditional kernel, the implementation policies, variant selection and
-// the launchers.  Each kernels_nu*.hip file instantiates the launchers for
-// one smoothness, so the heavy kernels compile in parallel.
+// the launchers.  Each kernels_*.hip file instantiates the launchers for one
+// covariance code (Matern smoothness or power exponential, with Euclidean or
+// great-circle distance), so the heavy kernels compile in parallel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,26 +21,28 @@
 namespace vecchia {
 
 // Implementation policies: how one conditional is evaluated by a workgroup.
-template <int NU, bool GRAD>
+template <int KC, bool GRAD>
 struct LdsImpl {
     static constexpr int NT = 256;
     static constexpr int WPE = 2;  // wavefronts per SIMD the register allocation targets
     static size_t smem(int m) { return lds_kernel_smem_bytes(m); }
-    static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int32_t m,
-                                  const Params &P, double *sm) {
-        return lds_conditional<NU, GRAD>(locs, z, nbr, i, m, P, sm);
+    static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int64_t n,
+                                  int32_t m, const double *qloc, const Params &P, double *sm) {
+        return lds_conditional<KC, GRAD>(locs, z, nbr, i, n, m, qloc, P, sm);
     }
 };
 
-template <int T, int W, int NU, bool GRAD>
+template <int T, int W, int KC, bool GRAD>
 struct TileImpl {
     static constexpr int NT = W * kWave;
-    static constexpr int WPE =
-        VECCHIA_WPE_OVERRIDE > 0 ? VECCHIA_WPE_OVERRIDE : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W));
-    static size_t smem(int) { return TileLds<T>::BYTES; }
-    static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int32_t m,
-                                  const Params &P, double *sm) {
-        return tile_conditional<T, W, NU, GRAD>(locs, z, nbr, i, m, P, sm);
+    static constexpr bool GCD = kc_gcd(KC);
+    static constexpr int WPE = VECCHIA_WPE_OVERRIDE > 0
+                                   ? VECCHIA_WPE_OVERRIDE
+                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD), GCD);
+    static size_t smem(int) { return TileLds<T, GCD>::BYTES; }
+    static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int64_t n,
+                                  int32_t m, const double *qloc, const Params &P, double *sm) {
+        return tile_conditional<T, W, KC, GRAD>(locs, z, nbr, i, n, m, qloc, P, sm);
     }
 };
 
@@ -60,7 +63,11 @@ struct FieldDev {
 //   batched mode: the items of a tile class, t in [0, item0[nfc]); item t lies
 //     in class field c (item0[c] <= t < item0[c+1]) = fields[fidx[c]], with
 //     theta index p and point i from t - item0[c] = p n + i; results go to row
-//     vals0 + p n + i of ell / g / flags, parameters to theta + 3 (eval0 + p).
+//     vals0 + p n + i of ell / g / flags, parameters to theta + 3 (eval0 + p);
+//   prediction mode (qlocs != NULL, single mode only): item t is prediction
+//     point t < nq at qlocs[t], conditioned on row t of nbr among the n
+//     points of locs / z; mean and variance go to pmean[t], pvar[t].
+// alpha is the power-exponential exponent (ignored by the Matern codes).
 struct KernelArgs {
     const double *locs, *z;
     const int32_t *nbr;
@@ -79,6 +86,10 @@ struct KernelArgs {
     int32_t *flags;
     unsigned long long *status;
     int64_t t0;
+    double alpha;
+    const double *qlocs;
+    int64_t nq;
+    double *pmean, *pvar;
 };
 
 // One workgroup per item (a point of one evaluation).  Failure is reported
@@ -115,16 +126,23 @@ __global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(I
         i = a.idx ? a.idx[t] : t;
         row = t;
     }
-    const Params P = load_params(theta);
+    const Params P = load_params(theta, a.alpha);
+    const bool pred = a.qlocs != nullptr;
+    const int64_t nitems = pred ? a.nq : n;
     CondOut o;
     bool bad = true;
-    if (P.valid && i >= 0 && i < n) {  // uniform over the workgroup
-        o = Impl::run(locs, z, nbr, i, m, P, smem);
+    if (P.valid && i >= 0 && i < nitems) {  // uniform over the workgroup
+        o = Impl::run(locs, z, nbr, i, n, m, pred ? a.qlocs + 2 * i : nullptr, P, smem);
         bad = o.bad;
     }
-    if (bad) o.ell = o.g0 = o.g1 = o.g2 = __builtin_nan("");
+    if (bad) o.ell = o.g0 = o.g1 = o.g2 = o.mean = o.var = __builtin_nan("");
     if (threadIdx.x == 0) {
-        a.ell[row * a.ell_stride] = o.ell;
+        if (pred) {
+            a.pmean[row] = o.mean;
+            a.pvar[row] = o.var;
+        } else {
+            a.ell[row * a.ell_stride] = o.ell;
+        }
         if (a.g) {
             a.g[row * a.g_stride + 0] = o.g0;
             a.g[row * a.g_stride + 1] = o.g1;
@@ -189,65 +207,71 @@ inline int default_variant(int m) {
     return V_TILE_W8;
 }
 
-template <int NU, bool GRAD, int T, int W>
+template <int KC, bool GRAD, int T, int W>
 int launch_tile(const EvalArgs &a, hipStream_t s) {
     if constexpr (W > 1 && tile_count(T) < W) {
         return VECCHIA_EUNSUPPORTED;
     } else if constexpr (tiles_per_wave(T, W) > 20) {
         return VECCHIA_EUNSUPPORTED;
     } else {
-        return launch_cond_impl<TileImpl<T, W, NU, GRAD>>(a, s);
+        return launch_cond_impl<TileImpl<T, W, KC, GRAD>>(a, s);
     }
 }
 
-template <int NU, bool GRAD, int W>
+template <int KC, bool GRAD, int W>
 int launch_tile_w(int T, const EvalArgs &a, hipStream_t s) {
 #ifdef VECCHIA_ONE_VARIANT
-    if (T == 8 && W == 4) return launch_tile<NU, GRAD, 8, 4>(a, s);
+    if (T == 8 && W == 4) return launch_tile<KC, GRAD, 8, 4>(a, s);
     return VECCHIA_EUNSUPPORTED;
 #else
     switch (T) {
-        case 1: return launch_tile<NU, GRAD, 1, W>(a, s);
-        case 2: return launch_tile<NU, GRAD, 2, W>(a, s);
-        case 3: return launch_tile<NU, GRAD, 3, W>(a, s);
-        case 4: return launch_tile<NU, GRAD, 4, W>(a, s);
-        case 5: return launch_tile<NU, GRAD, 5, W>(a, s);
-        case 6: return launch_tile<NU, GRAD, 6, W>(a, s);
-        case 7: return launch_tile<NU, GRAD, 7, W>(a, s);
-        case 8: return launch_tile<NU, GRAD, 8, W>(a, s);
-        case 9: return launch_tile<NU, GRAD, 9, W>(a, s);
-        case 10: return launch_tile<NU, GRAD, 10, W>(a, s);
-        case 11: return launch_tile<NU, GRAD, 11, W>(a, s);
+        case 1: return launch_tile<KC, GRAD, 1, W>(a, s);
+        case 2: return launch_tile<KC, GRAD, 2, W>(a, s);
+        case 3: return launch_tile<KC, GRAD, 3, W>(a, s);
+        case 4: return launch_tile<KC, GRAD, 4, W>(a, s);
+        case 5: return launch_tile<KC, GRAD, 5, W>(a, s);
+        case 6: return launch_tile<KC, GRAD, 6, W>(a, s);
+        case 7: return launch_tile<KC, GRAD, 7, W>(a, s);
+        case 8: return launch_tile<KC, GRAD, 8, W>(a, s);
+        case 9: return launch_tile<KC, GRAD, 9, W>(a, s);
+        case 10: return launch_tile<KC, GRAD, 10, W>(a, s);
+        case 11: return launch_tile<KC, GRAD, 11, W>(a, s);
         default: return VECCHIA_EUNSUPPORTED;
     }
 #endif
 }
 
-template <int NU, bool GRAD>
+template <int KC, bool GRAD>
 int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
     const int T = tile_rows(a.m_max);
     switch (variant) {
         case V_UNBLOCKED:
-            return launch_cond_impl<LdsImpl<NU, GRAD>>(a, s);
-        case V_TILE_W1: return launch_tile_w<NU, GRAD, 1>(T, a, s);
-        case V_TILE_W2: return launch_tile_w<NU, GRAD, 2>(T, a, s);
-        case V_TILE_W4: return launch_tile_w<NU, GRAD, 4>(T, a, s);
-        case V_TILE_W8: return launch_tile_w<NU, GRAD, 8>(T, a, s);
+            return launch_cond_impl<LdsImpl<KC, GRAD>>(a, s);
+        case V_TILE_W1: return launch_tile_w<KC, GRAD, 1>(T, a, s);
+        case V_TILE_W2: return launch_tile_w<KC, GRAD, 2>(T, a, s);
+        case V_TILE_W4: return launch_tile_w<KC, GRAD, 4>(T, a, s);
+        case V_TILE_W8: return launch_tile_w<KC, GRAD, 8>(T, a, s);
         default: return VECCHIA_EUNSUPPORTED;
     }
 }
 
 // Defined in vecchia.hip: smoothness code (0, 1, 2 for nu = 0.5, 1.5, 2.5;
 // -1 otherwise), the variant a launch uses for (m, gradient), the host-side
-// variant table, and the launcher for any smoothness.
+// variant table, and the launcher for any covariance code (0..7).
 int nu_code(double nu);
 int resolve_variant(int m, bool grad, int requested);
 extern int g_variant[2][VECCHIA_MAX_M + 1];
-int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_any(int kc, bool grad, int variant, const EvalArgs &a, hipStream_t s);
 
-// Defined in kernels_nu05.hip, kernels_nu15.hip and kernels_nu25.hip.
+// Defined in kernels_nu05.hip, kernels_nu15.hip, kernels_nu25.hip (Matern,
+// Euclidean) and kernels_kc3.hip .. kernels_kc7.hip (the other codes).
 int launch_nu05(bool grad, int variant, const EvalArgs &a, hipStream_t s);
 int launch_nu15(bool grad, int variant, const EvalArgs &a, hipStream_t s);
 int launch_nu25(bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_kc3(bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_kc4(bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_kc5(bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_kc6(bool grad, int variant, const EvalArgs &a, hipStream_t s);
+int launch_kc7(bool grad, int variant, const EvalArgs &a, hipStream_t s);
 
 }  // namespace vecchia

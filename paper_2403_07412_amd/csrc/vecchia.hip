@@ -42,12 +42,37 @@ int nu_code(double nu) {
     return -1;
 }
 
-int launch_any(int nuc, bool grad, int variant, const EvalArgs &a, hipStream_t s) {
-    switch (nuc) {
+int launch_any(int kc, bool grad, int variant, const EvalArgs &a, hipStream_t s) {
+    switch (kc) {
         case 0: return launch_nu05(grad, variant, a, s);
         case 1: return launch_nu15(grad, variant, a, s);
-        default: return launch_nu25(grad, variant, a, s);
+        case 2: return launch_nu25(grad, variant, a, s);
+        case 3: return launch_kc3(grad, variant, a, s);
+        case 4: return launch_kc4(grad, variant, a, s);
+        case 5: return launch_kc5(grad, variant, a, s);
+        case 6: return launch_kc6(grad, variant, a, s);
+        case 7: return launch_kc7(grad, variant, a, s);
+        default: return VECCHIA_EINVAL;
     }
+}
+
+// Covariance code of a model (family + 4 metric, as kc_family / kc_gcd
+// read it) and its power-exponential exponent; -1 for an invalid model.
+int cov_code(const vecchia_cov *cov, double *alpha) {
+    if (!cov || (cov->metric != VECCHIA_EUCLIDEAN && cov->metric != VECCHIA_GREAT_CIRCLE)) return -1;
+    int fam;
+    if (cov->family == VECCHIA_MATERN) {
+        fam = nu_code(cov->smoothness);
+        if (fam < 0) return -1;
+        *alpha = 1.0;
+    } else if (cov->family == VECCHIA_POWEXP) {
+        if (!(cov->smoothness > 0.0 && cov->smoothness <= 2.0)) return -1;
+        fam = 3;
+        *alpha = cov->smoothness;
+    } else {
+        return -1;
+    }
+    return fam + 4 * (cov->metric == VECCHIA_GREAT_CIRCLE ? 1 : 0);
 }
 
 }  // namespace vecchia
@@ -113,11 +138,11 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const double
     finalize_segment(partial, pfail, nblocks, theta, out, grad, status);
 }
 
-int check_common(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+int check_common(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, int kc,
                  const double *theta) {
     if (n < 0 || m < 0) return VECCHIA_EINVAL;
     if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
-    if (nu_code(nu) < 0) return VECCHIA_EINVAL;
+    if (kc < 0) return VECCHIA_EINVAL;
     if (!theta) return VECCHIA_EINVAL;
     if (n > 0 && (!locs || !z)) return VECCHIA_EINVAL;
     if (n > 1 && m > 0 && !nbr) return VECCHIA_EINVAL;
@@ -125,10 +150,10 @@ int check_common(const double *locs, const double *z, const int32_t *nbr, int64_
     return VECCHIA_OK;
 }
 
-int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, int kc, double alpha,
             const double *theta, double *out, double *grad, int64_t *status, void *ws, size_t ws_bytes,
             void *stream, bool with_grad, int variant) {
-    int rc = check_common(locs, z, nbr, n, m, nu, theta);
+    int rc = check_common(locs, z, nbr, n, m, kc, theta);
     if (rc != VECCHIA_OK) return rc;
     if (!out || !status || (with_grad && !grad)) return VECCHIA_EINVAL;
     WsLayout L = ws_layout(ws, n);
@@ -147,10 +172,11 @@ int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, 
     a.k.g = L.vals + 1;
     a.k.g_stride = 4;
     a.k.flags = L.flags;
+    a.k.alpha = alpha;
     a.t_begin = 0;
     a.t_end = n;
     a.m_max = m;
-    rc = launch_any(nu_code(nu), with_grad, resolve_variant(m, with_grad, variant), a, s);
+    rc = launch_any(kc, with_grad, resolve_variant(m, with_grad, variant), a, s);
     if (rc != VECCHIA_OK) return rc;
     const int64_t nb = num_reduce_blocks(n);
     if (nb > 0)
@@ -161,10 +187,10 @@ int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, 
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
 
-int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, int kc, double alpha,
               const double *theta, const int64_t *idx, int64_t nidx, double *terms, double *gterms,
               int64_t *status, void *stream, int variant) {
-    int rc = check_common(locs, z, nbr, n, m, nu, theta);
+    int rc = check_common(locs, z, nbr, n, m, kc, theta);
     if (rc != VECCHIA_OK) return rc;
     if (nidx < 0 || !status || (nidx > 0 && !terms) || (!idx && nidx != n)) return VECCHIA_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -183,11 +209,46 @@ int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n
     a.k.g = gterms;
     a.k.g_stride = 3;
     a.k.status = st;
+    a.k.alpha = alpha;
     a.t_begin = 0;
     a.t_end = nidx;
     a.m_max = m;
     hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, s, st);
-    rc = launch_any(nu_code(nu), g, resolve_variant(m, g, variant), a, s);
+    rc = launch_any(kc, g, resolve_variant(m, g, variant), a, s);
+    if (rc != VECCHIA_OK) return rc;
+    hipLaunchKernelGGL(status_fix_kernel, dim3(1), dim3(64), 0, s, st, theta);
+    return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+}
+
+int run_predict(const double *locs, const double *z, int64_t n, const double *qlocs, int64_t nq,
+                const int32_t *nbr, int32_t m, int kc, double alpha, const double *theta, double *mean, double *var,
+                int64_t *status, void *stream) {
+    if (n < 0 || nq < 0 || m < 0 || kc < 0 || !theta || !status) return VECCHIA_EINVAL;
+    if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
+    if (nq > (int64_t)INT32_MAX * kChunk) return VECCHIA_EUNSUPPORTED;
+    if (nq > 0 && (!qlocs || !mean || !var)) return VECCHIA_EINVAL;
+    const int32_t k = (int32_t)std::min<int64_t>(n, m);
+    if (k > 0 && (!locs || !z || !nbr)) return VECCHIA_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *st = (unsigned long long *)status;
+    EvalArgs a{};
+    a.k.locs = locs;
+    a.k.z = z;
+    a.k.nbr = nbr;
+    a.k.n = n;
+    a.k.m = m;
+    a.k.theta = theta;
+    a.k.status = st;
+    a.k.alpha = alpha;
+    a.k.qlocs = qlocs;
+    a.k.nq = nq;
+    a.k.pmean = mean;
+    a.k.pvar = var;
+    a.t_begin = 0;
+    a.t_end = nq;
+    a.m_max = m;
+    hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, s, st);
+    const int rc = launch_any(kc, false, resolve_variant(m, false, V_AUTO), a, s);
     if (rc != VECCHIA_OK) return rc;
     hipLaunchKernelGGL(status_fix_kernel, dim3(1), dim3(64), 0, s, st, theta);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
@@ -219,19 +280,46 @@ size_t vecchia_workspace_size(int64_t n, int32_t m) {
 
 int vecchia_loglik(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                    const double *theta, double *out, int64_t *status, void *ws, size_t ws_bytes, void *stream) {
-    return run_sum(locs, z, nbr, n, m, nu, theta, out, nullptr, status, ws, ws_bytes, stream, false, V_AUTO);
+    return run_sum(locs, z, nbr, n, m, nu_code(nu), 1.0, theta, out, nullptr, status, ws, ws_bytes, stream, false,
+                   V_AUTO);
 }
 
 int vecchia_loglik_grad(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                         const double *theta, double *out, double *grad, int64_t *status, void *ws,
                         size_t ws_bytes, void *stream) {
-    return run_sum(locs, z, nbr, n, m, nu, theta, out, grad, status, ws, ws_bytes, stream, true, V_AUTO);
+    return run_sum(locs, z, nbr, n, m, nu_code(nu), 1.0, theta, out, grad, status, ws, ws_bytes, stream, true,
+                   V_AUTO);
 }
 
 int vecchia_loglik_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                          double nu, const double *theta, const int64_t *idx, int64_t nidx, double *terms,
                          double *gterms, int64_t *status, void *stream) {
-    return run_terms(locs, z, nbr, n, m, nu, theta, idx, nidx, terms, gterms, status, stream, V_AUTO);
+    return run_terms(locs, z, nbr, n, m, nu_code(nu), 1.0, theta, idx, nidx, terms, gterms, status, stream, V_AUTO);
+}
+
+int vecchia_loglik_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                       const vecchia_cov *cov, const double *theta, double *out, double *grad, int64_t *status,
+                       void *ws, size_t ws_bytes, void *stream) {
+    double alpha = 1.0;
+    const int kc = cov_code(cov, &alpha);
+    return run_sum(locs, z, nbr, n, m, kc, alpha, theta, out, grad, status, ws, ws_bytes, stream, grad != nullptr,
+                   V_AUTO);
+}
+
+int vecchia_loglik_terms_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                             const vecchia_cov *cov, const double *theta, const int64_t *idx, int64_t nidx,
+                             double *terms, double *gterms, int64_t *status, void *stream) {
+    double alpha = 1.0;
+    const int kc = cov_code(cov, &alpha);
+    return run_terms(locs, z, nbr, n, m, kc, alpha, theta, idx, nidx, terms, gterms, status, stream, V_AUTO);
+}
+
+int vecchia_predict(const double *locs, const double *z, int64_t n, const double *qlocs, int64_t nq,
+                    const int32_t *nbr, int32_t m, const vecchia_cov *cov, const double *theta, double *mean,
+                    double *var, int64_t *status, void *stream) {
+    double alpha = 1.0;
+    const int kc = cov_code(cov, &alpha);
+    return run_predict(locs, z, n, qlocs, nq, nbr, m, kc, alpha, theta, mean, var, status, stream);
 }
 
 int vecchia_set_variant(int32_t m, int32_t with_grad, int32_t variant) {
@@ -257,8 +345,8 @@ int vecchia_loglik_variant(const double *locs, const double *z, const int32_t *n
     if (variant < V_AUTO || variant > V_TILE_W8) return VECCHIA_EINVAL;
     if (variant != V_AUTO && m >= 0 && m <= VECCHIA_MAX_M && !variant_feasible(variant, m))
         return VECCHIA_EUNSUPPORTED;
-    return run_sum(locs, z, nbr, n, m, nu, theta, out, grad, status, ws, ws_bytes, stream, grad != nullptr,
-                   variant);
+    return run_sum(locs, z, nbr, n, m, nu_code(nu), 1.0, theta, out, grad, status, ws, ws_bytes, stream,
+                   grad != nullptr, variant);
 }
 
 int vecchia_loglik_terms_variant(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
@@ -267,7 +355,8 @@ int vecchia_loglik_terms_variant(const double *locs, const double *z, const int3
     if (variant < V_AUTO || variant > V_TILE_W8) return VECCHIA_EINVAL;
     if (variant != V_AUTO && m >= 0 && m <= VECCHIA_MAX_M && !variant_feasible(variant, m))
         return VECCHIA_EUNSUPPORTED;
-    return run_terms(locs, z, nbr, n, m, nu, theta, idx, nidx, terms, gterms, status, stream, variant);
+    return run_terms(locs, z, nbr, n, m, nu_code(nu), 1.0, theta, idx, nidx, terms, gterms, status, stream,
+                     variant);
 }
 
 }  // extern "C"
