@@ -151,6 +151,57 @@ def preprocess_times(v, f, locs, stream, reps: int = 3):
             "knn_cpu_threads": min(os.cpu_count() or 1, 16), "knn_equals_cpu_sets": same}
 
 
+def realdata_times(v, stream, reps: int = 2):
+    """The real-data configuration of Sec. V-C on synthetic points: 250,000 observed and 25,000
+    prediction points as (longitude, latitude) over a 10 x 10 degree box, power-exponential covariance on
+    great-circle distances, m = 60.  Best-of-`reps` HIP-event timings of each step: great-circle
+    conditioning sets, log-likelihood + gradient, prediction-point neighbour sets, kriging."""
+    import torch
+
+    import workloads as wl
+
+    rng = np.random.default_rng(2403)
+    n, nq, m = 250_000, 25_000, 60
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(wl.lonlat_locations(rng, n)).to(dev)
+    Z = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    Q = torch.from_numpy(wl.lonlat_locations(rng, nq)).to(dev)
+    cov = (v.POWEXP, v.GREAT_CIRCLE, 0.9)
+    th = torch.tensor([1.0, 80.0, 0.05], dtype=torch.float64, device=dev)
+
+    def best_ms(fn):
+        ts = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return min(ts[1:])
+
+    nbr = torch.empty((n, m), dtype=torch.int32, device=dev)
+    kws = torch.empty(v.vecchia_knn_workspace_size(n), dtype=torch.uint8, device=dev)
+    knn_ms = best_ms(lambda: v.vecchia_knn(L, m, out=nbr, ws=kws, stream=stream, metric=v.GREAT_CIRCLE))
+    ws = torch.empty(v.vecchia_workspace_size(n, m), dtype=torch.uint8, device=dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(3, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int64, device=dev)
+    ll_ms = best_ms(lambda: v.vecchia_loglik_cov(L, Z, nbr, m, cov, th, with_grad=True, out=out, grad=grad,
+                                                 status=st, ws=ws, stream=stream))
+    qnbr = torch.empty((nq, m), dtype=torch.int32, device=dev)
+    q_ms = best_ms(lambda: v.vecchia_knn_query(L, Q, m, metric=v.GREAT_CIRCLE, out=qnbr, ws=kws, stream=stream))
+    mean = torch.empty(nq, dtype=torch.float64, device=dev)
+    var = torch.empty(nq, dtype=torch.float64, device=dev)
+    pst = torch.empty(1, dtype=torch.int64, device=dev)
+    p_ms = best_ms(lambda: v.vecchia_predict(L, Z, Q, qnbr, m, cov, th, mean=mean, var=var, status=pst,
+                                             stream=stream))
+    ok = int(st.item()) == 0 and int(pst.item()) == 0 and bool(torch.isfinite(mean).all())
+    return {"workload": "n250K_q25K_m60 power-exponential alpha=0.9, great-circle", "knn_ms": knn_ms,
+            "loglik_grad_ms": ll_ms, "loglik_grad_cond_per_s": n / (ll_ms * 1e-3), "knn_query_ms": q_ms,
+            "predict_ms": p_ms, "predict_per_s": nq / (p_ms * 1e-3), "status_ok": ok}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +215,8 @@ def main():
                     help="conditionals the autotuner times per variant (0: the whole field, so that every launch "
                          "of the chosen kernel in a profile of this command has the full size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-realdata", action="store_true",
+                    help="skip the real-data configuration leg (power exponential, great-circle, kriging)")
     ap.add_argument("--no-preprocess", action="store_true",
                     help="skip timing the GPU conditioning-set search and Morton ordering of the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -293,6 +346,8 @@ def main():
         del src, dst
     if not args.no_preprocess:
         rec["preprocess"] = preprocess_times(v, f, locs, stream)
+    if not args.no_realdata:
+        rec["realdata"] = realdata_times(v, stream)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(f, True)
     print(json.dumps(rec), flush=True)

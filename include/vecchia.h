@@ -424,6 +424,12 @@ int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t
                 const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
                 double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes, void *stream);
 
+/* vecchia_mle under any covariance model (smoothness fixed, as vecchia_loglik_cov). */
+int vecchia_mle_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                    const vecchia_cov *cov, const double *theta0, const vecchia_mle_options *options, double *theta,
+                    double *loglik, double *grad, int32_t *iterations, int32_t *evaluations, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /*
  * Exact Gaussian-process log-likelihood, Eq. (1), for the KL divergence of
  * Eq. (9): KL(N_0 || N_a) = l_0(theta; 0) - l_a(theta; 0), the exact minus

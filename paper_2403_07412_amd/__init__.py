@@ -147,6 +147,10 @@ def _load():
         lib.vecchia_dense_logdet.restype = ctypes.c_int
         lib.vecchia_dense_logdet.argtypes = [P, I64, I64, P, P, P, P, P, SZ, P]
         CP = ctypes.POINTER(Cov)
+        lib.vecchia_mle_cov.restype = ctypes.c_int
+        lib.vecchia_mle_cov.argtypes = [P, P, P, I64, I32, CP, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
+                                        ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
+                                        ctypes.POINTER(I32), P, SZ, P]
         lib.vecchia_loglik_cov.restype = ctypes.c_int
         lib.vecchia_loglik_cov.argtypes = [P, P, P, I64, I32, CP, P, P, P, P, P, SZ, P]
         lib.vecchia_loglik_terms_cov.restype = ctypes.c_int
@@ -667,10 +671,13 @@ def mle_default_options() -> MleOptions:
     return opt
 
 
-def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = None, ws=None, stream=None):
-    """Maximum-likelihood (sigma2, beta, tau2) at fixed nu.  Returns a dict with theta, loglik, grad,
-    iterations and evaluations."""
+def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = None, ws=None, stream=None,
+                cov=None):
+    """Maximum-likelihood (sigma2, beta, tau2) at fixed nu (Matern, Euclidean), or under the covariance
+    model cov = (family, metric, smoothness) when given (then nu is ignored).  Returns a dict with theta,
+    loglik, grad, iterations and evaluations."""
     n = _as_inputs(locs, z, nbr, m)
+    c = _cov(cov if cov is not None else (MATERN, EUCLIDEAN, nu))
     need = int(_load().vecchia_mle_workspace_size(n, m))
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=locs.device)
@@ -680,9 +687,9 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
     ll = ctypes.c_double()
     it = ctypes.c_int32()
     ev = ctypes.c_int32()
-    rc = _load().vecchia_mle(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, int(m), float(nu), th0,
-                             ctypes.byref(options) if options is not None else None, th, ctypes.byref(ll), gr,
-                             ctypes.byref(it), ctypes.byref(ev), _ptr(ws), ws.numel(), _stream(stream))
+    rc = _load().vecchia_mle_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, int(m), ctypes.byref(c),
+                                 th0, ctypes.byref(options) if options is not None else None, th, ctypes.byref(ll),
+                                 gr, ctypes.byref(it), ctypes.byref(ev), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "vecchia_mle")
     return {"theta": np.array(th[:]), "loglik": ll.value, "grad": np.array(gr[:]), "iterations": it.value,
             "evaluations": ev.value}

@@ -1,10 +1,10 @@
-// Maximum-likelihood estimation of (sigma2, beta, tau2) at fixed smoothness:
-// the use the Vecchia log-likelihood is built for (Sec. V fits the Matern
-// parameters by maximising it).  The paper drives a derivative-free NLopt
+// Maximum-likelihood estimation of (sigma2, beta, tau2) at fixed smoothness,
+// for any covariance model: the use the Vecchia log-likelihood is built for
+// (Sec. V fits the Matern and power-exponential parameters by maximising it).  The paper drives a derivative-free NLopt
 // search; here the fused value + gradient evaluation feeds a projected
 // limited-memory BFGS in log-parameters, phi = log theta, inside bounds.
 //
-// Host code only: every evaluation is one vecchia_loglik_grad call on the
+// Host code only: every evaluation is one vecchia_loglik_cov call on the
 // caller's stream, followed by a 40-byte read-back and a stream sync.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,7 +34,7 @@ struct Problem {
     const int32_t *nbr;
     int64_t n;
     int32_t m;
-    double nu;
+    vecchia_cov cov;
     char *ws;
     size_t ws_bytes;
     hipStream_t s;
@@ -48,8 +48,8 @@ struct Problem {
         int64_t *d_status = (int64_t *)(d_out + 4);
         double *d_theta = d_out + 5;
         if (hipMemcpyAsync(d_theta, th, sizeof(th), hipMemcpyHostToDevice, s) != hipSuccess) return VECCHIA_EHIP;
-        const int rc = vecchia_loglik_grad(locs, z, nbr, n, m, nu, d_theta, d_out, d_grad, d_status, ws + kScratch,
-                                           ws_bytes - kScratch, s);
+        const int rc = vecchia_loglik_cov(locs, z, nbr, n, m, &cov, d_theta, d_out, d_grad, d_status, ws + kScratch,
+                                          ws_bytes - kScratch, s);
         if (rc != VECCHIA_OK) return rc;
         double host[5];
         int64_t status = 0;
@@ -96,11 +96,11 @@ extern "C" void vecchia_mle_default_options(vecchia_mle_options *opt) {
 
 extern "C" size_t vecchia_mle_workspace_size(int64_t n, int32_t m) { return kScratch + vecchia_workspace_size(n, m); }
 
-extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
-                           const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
-                           double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes,
-                           void *stream) {
-    if (!theta0 || !theta || !locs || !z || (m > 0 && !nbr) || n < 1 || m < 0) return VECCHIA_EINVAL;
+extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                               const vecchia_cov *cov, const double *theta0, const vecchia_mle_options *options,
+                               double *theta, double *loglik, double *grad, int32_t *iterations,
+                               int32_t *evaluations, void *ws, size_t ws_bytes, void *stream) {
+    if (!cov || !theta0 || !theta || !locs || !z || (m > 0 && !nbr) || n < 1 || m < 0) return VECCHIA_EINVAL;
     vecchia_mle_options opt;
     if (options) {
         opt = *options;
@@ -119,7 +119,7 @@ extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *n
         phi[p] = std::min(hi[p], std::max(lo[p], std::log(theta0[p])));
     }
     if (!ws || ws_bytes < vecchia_mle_workspace_size(n, m)) return VECCHIA_EWORKSPACE;
-    Problem pb{locs, z, nbr, n, m, nu, (char *)ws, ws_bytes, (hipStream_t)stream};
+    Problem pb{locs, z, nbr, n, m, *cov, (char *)ws, ws_bytes, (hipStream_t)stream};
 
     Eval cur;
     int rc = pb.eval(phi, cur);
@@ -227,4 +227,13 @@ extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *n
     if (iterations) *iterations = iter;
     if (evaluations) *evaluations = pb.evals;
     return VECCHIA_OK;
+}
+
+extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
+                           const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
+                           double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes,
+                           void *stream) {
+    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
+    return vecchia_mle_cov(locs, z, nbr, n, m, &cov, theta0, options, theta, loglik, grad, iterations, evaluations,
+                           ws, ws_bytes, stream);
 }

@@ -80,3 +80,43 @@ def test_mle_rejects_bad_start(v):
     opt.history = 0
     with pytest.raises(v.VecchiaError):
         v.vecchia_mle(*args, (1.0, 0.1, 0.01), options=opt)
+
+
+def test_mle_power_exponential_great_circle_matches_oracle_fit(v):
+    """The real-data model of Sec. V-C: power exponential on great-circle distances, alpha fixed."""
+    import torch
+    from sklearn.metrics.pairwise import haversine_distances
+    rng = np.random.default_rng(620)
+    n, m, alpha = 1200, 25, 0.9
+    locs = np.column_stack([rng.uniform(-95.0, -85.0, n), rng.uniform(30.0, 40.0, n)])
+    D = oracle.EARTH_RADIUS_KM * haversine_distances(np.radians(locs[:, ::-1]))
+    truth = (1.5, 80.0, 0.05)
+    S = truth[0] * np.exp(-D ** alpha / truth[1]) + truth[2] * np.eye(n)
+    z = np.linalg.cholesky(S) @ rng.standard_normal(n)
+    cov = (oracle.POWEXP, oracle.GREAT_CIRCLE, alpha)
+    nbr = oracle.knn_rows(locs, m, metric=oracle.GREAT_CIRCLE)
+    theta0 = np.array([0.5, 30.0, 0.2])
+    dev = torch.device("cuda:0")
+    res = v.vecchia_mle(torch.from_numpy(locs).to(dev), torch.from_numpy(z).to(dev), torch.from_numpy(nbr).to(dev),
+                        m, 0.0, theta0, cov=cov)
+    print("gpu fit", res, flush=True)
+    opt = v.mle_default_options()
+    lower, upper = np.array(opt.lower[:]), np.array(opt.upper[:])
+    from scipy.optimize import minimize
+
+    def fun(phi):
+        th = np.exp(phi)
+        try:
+            ell, g = oracle.loglik_cov(locs, z, nbr, m, cov, th, with_grad=True, threads=16)
+        except oracle.OracleError:
+            return np.inf, np.zeros(3)
+        return -ell / n, -g * th / n
+
+    ref = minimize(fun, np.log(theta0), jac=True, method="L-BFGS-B", bounds=list(zip(np.log(lower), np.log(upper))),
+                   options={"maxiter": 1000, "ftol": 1e-16, "gtol": 1e-11})
+    th_ref, ll_ref = np.exp(ref.x), -ref.fun * n
+    print("oracle fit", th_ref, ll_ref, flush=True)
+    ll_at = oracle.loglik_cov(locs, z, nbr, m, cov, res["theta"])
+    assert abs(res["loglik"] - ll_at) <= 1e-10 * abs(ll_at)
+    assert res["loglik"] >= ll_ref - 1e-9 * abs(ll_ref)
+    np.testing.assert_allclose(res["theta"], th_ref, rtol=2e-3)

@@ -81,6 +81,12 @@ def uniform_locations(rng: np.random.Generator, n: int) -> np.ndarray:
     return rng.uniform(0.0, 1.0, size=(n, 2))
 
 
+def lonlat_locations(rng: np.random.Generator, n: int, lon=(-95.0, -85.0), lat=(30.0, 40.0)) -> np.ndarray:
+    """(longitude, latitude) in degrees, uniform over a lon x lat box; the default 10 x 10 degree box has
+    the extent of a regional field such as the soil-moisture data of the real-data study."""
+    return np.column_stack([rng.uniform(lon[0], lon[1], n), rng.uniform(lat[0], lat[1], n)])
+
+
 def jittered_grid_locations(rng: np.random.Generator, n: int, jitter: float = 0.4) -> np.ndarray:
     """sqrt(n) x sqrt(n) cell centres ((i+1/2)/g, (j+1/2)/g) plus U(-jitter/g, +jitter/g) per coordinate."""
     g = math.isqrt(n)
