@@ -384,6 +384,37 @@ size_t vecchia_morton_workspace_size(int64_t n);
 int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Approximate maxmin ordering: maxmin orders points so that each one is as
+ * far as possible from those before it, the ordering Sec. IV-A names as
+ * accurate but too costly at scale.  This approximation elects points in
+ * rounds over finer and finer grids:
+ *   - Round r uses G x G square cells, G = 2^min(r, Lmax), on the square box
+ *     whose lower-left corner is that of the bounding box and whose side w is
+ *     the larger side of the bounding box (1 when zero).  Lmax is the least
+ *     L >= 0 with 4^L >= n, plus 1, at most 15.
+ *   - A point's cell per axis is min(floor((v - v0) / w * G), G - 1), or 0
+ *     when negative or NaN.
+ *   - Every cell elects its unselected point with the least squared distance
+ *     to the cell centre v0 + (c + 1/2) w / G, taken as dx*dx + dy*dy with
+ *     every operation rounded; ties go to the lower index.
+ *   - A round's points follow all earlier rounds, in ascending
+ *     mix64(seed XOR i), the splitmix64 finaliser (a bijection).
+ *   - After Lmax + 33 rounds, the remaining points follow in that key order.
+ * The first points of the ordering are thus spread over the domain at every
+ * scale, as maxmin's are.
+ *   locs [dev] double[n][2];  perm [dev] int64[n] receives the permutation
+ *   ws   [dev] at least vecchia_maxmin_workspace_size(n) bytes: 12 bytes
+ *        per cell of the finest grid (4 to 16 cells per point) plus sort
+ *        buffers of about 40 bytes per point
+ * Synchronises the stream once per round (at most Lmax + 34 rounds).  Exact:
+ * equal to the definition.  Returns VECCHIA_OK, VECCHIA_EINVAL (n < 0,
+ * n > 2^31 - 1, null pointers), VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+size_t vecchia_maxmin_workspace_size(int64_t n);
+int vecchia_maxmin_order(const double *locs, int64_t n, uint64_t seed, int64_t *perm, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
  * Maximum-likelihood fit of theta = (sigma2, beta, tau2) at fixed nu, the use
  * of the likelihood in Sec. V (the paper drives NLopt without derivatives;
  * this driver uses the fused gradient).  Projected limited-memory BFGS in

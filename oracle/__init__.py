@@ -69,6 +69,8 @@ def _load():
         lib.oracle_knn_rows_metric.argtypes = [P, I64, I32, I32, P, I64, P, I32]
         lib.oracle_knn_query.restype = I64
         lib.oracle_knn_query.argtypes = [P, I64, P, I64, I32, I32, P, I32]
+        lib.oracle_maxmin_order.restype = I64
+        lib.oracle_maxmin_order.argtypes = [P, I64, ctypes.c_uint64, P]
         lib.oracle_predict.restype = I64
         lib.oracle_predict.argtypes = [P, P, I64, P, I64, P, I32, I32, I32, D, P, P, P, I32]
         _lib = lib
@@ -276,6 +278,18 @@ def morton_order(locs):
     n = locs.shape[0]
     perm = np.empty(max(n, 1), dtype=np.int64)
     rc = _load().oracle_morton_order(locs.ctypes.data, n, perm.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return perm[:n]
+
+
+def maxmin_order(locs, seed: int = 0):
+    """Approximate maxmin ordering (rounds of per-cell elections over finer and finer grids, each round in
+    hashed-index order); returns the permutation."""
+    locs = np.ascontiguousarray(locs, dtype=np.float64)
+    n = locs.shape[0]
+    perm = np.empty(max(n, 1), dtype=np.int64)
+    rc = _load().oracle_maxmin_order(locs.ctypes.data, n, ctypes.c_uint64(seed & (2 ** 64 - 1)), perm.ctypes.data)
     if rc != 0:
         raise OracleError(rc)
     return perm[:n]

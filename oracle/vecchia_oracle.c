@@ -722,6 +722,116 @@ int64_t oracle_morton_order(const double *locs, int64_t n, int64_t *perm) {
 }
 
 /*
+ * Approximate maxmin ordering (the ordering Sec. IV-A names as accurate but
+ * too costly at scale), as defined for this library: points are elected in
+ * rounds r = 0, 1, ... over grids of G = 2^l(r) x 2^l(r) square cells,
+ * l(r) = min(r, Lmax), on the square box [x0, x0 + w] x [y0, y0 + w] with
+ * (x0, y0) the lower-left of the bounding box and w its larger side (1 when
+ * zero).  Lmax is the least L >= 0 with 4^L >= n, plus 1, at most 15.  A point's
+ * cell is c = min(floor((x - x0) / w * G), G - 1) per axis; in each round
+ * every cell elects, among its unselected points, the one with the least
+ * squared distance to the cell centre (x0 + (c + 1/2) w / G, each product
+ * and sum rounded, no contraction), ties by index.  The points elected in a
+ * round follow all earlier rounds, in ascending order of
+ * key(i) = mix64(seed XOR i) (a bijection on 64-bit words, the splitmix64
+ * finaliser).  After Lmax + 33 rounds any points left follow in the same
+ * key order.  perm receives the point indices in order.  Returns 0,
+ * ORACLE_EINVAL or ORACLE_ENOMEM.
+ */
+static uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    uint64_t key;
+    int64_t idx;
+} hkey_t;
+
+static int hkey_cmp(const void *a, const void *b) {
+    const hkey_t *x = (const hkey_t *)a, *y = (const hkey_t *)b;
+    return (x->key > y->key) - (x->key < y->key);
+}
+
+static int64_t maxmin_cell(double v, double v0, double w, int64_t G) {
+    double f = floor((v - v0) / w * (double)G);
+    if (!(f >= 0)) f = 0; /* negative or NaN */
+    if (f > (double)(G - 1)) f = (double)(G - 1);
+    return (int64_t)f;
+}
+
+int64_t oracle_maxmin_order(const double *locs, int64_t n, uint64_t seed, int64_t *perm) {
+    if (n < 0 || (n > 0 && (!locs || !perm))) return ORACLE_EINVAL;
+    if (n == 0) return 0;
+    double x0 = locs[0], x1 = locs[0], y0 = locs[1], y1 = locs[1];
+    for (int64_t i = 1; i < n; ++i) {
+        if (locs[2 * i] < x0) x0 = locs[2 * i];
+        if (locs[2 * i] > x1) x1 = locs[2 * i];
+        if (locs[2 * i + 1] < y0) y0 = locs[2 * i + 1];
+        if (locs[2 * i + 1] > y1) y1 = locs[2 * i + 1];
+    }
+    double w = (x1 - x0 > y1 - y0) ? x1 - x0 : y1 - y0;
+    if (!(w > 0)) w = 1.0;
+    int lmax = 0;
+    while (lmax < 14 && ((int64_t)1 << (2 * lmax)) < n) ++lmax;
+    lmax += 1;
+    const int64_t gmax = (int64_t)1 << lmax;
+    char *sel = (char *)calloc((size_t)n, 1);
+    double *bd = (double *)malloc((size_t)(gmax * gmax) * sizeof(double));
+    int64_t *bi = (int64_t *)malloc((size_t)(gmax * gmax) * sizeof(int64_t));
+    hkey_t *grp = (hkey_t *)malloc((size_t)n * sizeof(hkey_t));
+    if (!sel || !bd || !bi || !grp) {
+        free(sel); free(bd); free(bi); free(grp);
+        return ORACLE_ENOMEM;
+    }
+    int64_t done = 0;
+    for (int r = 0; done < n; ++r) {
+        int64_t cnt = 0;
+        if (r < lmax + 33) {
+            const int l = r < lmax ? r : lmax;
+            const int64_t G = (int64_t)1 << l;
+            for (int64_t c = 0; c < G * G; ++c) bi[c] = -1;
+            for (int64_t i = 0; i < n; ++i) {
+                if (sel[i]) continue;
+                const int64_t cx = maxmin_cell(locs[2 * i], x0, w, G);
+                const int64_t cy = maxmin_cell(locs[2 * i + 1], y0, w, G);
+                const double dx = locs[2 * i] - (x0 + ((double)cx + 0.5) * w / (double)G);
+                const double dy = locs[2 * i + 1] - (y0 + ((double)cy + 0.5) * w / (double)G);
+                const double d = dx * dx + dy * dy;
+                const int64_t c = cy * G + cx;
+                /* i ascends: among equal distances the earlier index stays */
+                if (bi[c] < 0 || d < bd[c]) {
+                    bd[c] = d;
+                    bi[c] = i;
+                }
+            }
+            for (int64_t c = 0; c < G * G; ++c)
+                if (bi[c] >= 0) {
+                    grp[cnt].key = mix64(seed ^ (uint64_t)bi[c]);
+                    grp[cnt].idx = bi[c];
+                    ++cnt;
+                }
+        } else {
+            for (int64_t i = 0; i < n; ++i)
+                if (!sel[i]) {
+                    grp[cnt].key = mix64(seed ^ (uint64_t)i);
+                    grp[cnt].idx = i;
+                    ++cnt;
+                }
+        }
+        qsort(grp, (size_t)cnt, sizeof(hkey_t), hkey_cmp);
+        for (int64_t t = 0; t < cnt; ++t) {
+            sel[grp[t].idx] = 1;
+            perm[done + t] = grp[t].idx;
+        }
+        done += cnt;
+    }
+    free(sel); free(bd); free(bi); free(grp);
+    return 0;
+}
+
+/*
  * Exact log-likelihood, Eq. (1): l = -1/2 (n log 2 pi + log det Sigma +
  * z^T Sigma^{-1} z) with Sigma the full covariance of all n points (the
  * covariance above, nugget on the diagonal), by a dense Cholesky-Banachiewicz

@@ -126,6 +126,10 @@ def _load():
         lib.vecchia_knn_workspace_size.argtypes = [I64]
         lib.vecchia_knn.restype = ctypes.c_int
         lib.vecchia_knn.argtypes = [P, I64, I32, P, P, SZ, P]
+        lib.vecchia_maxmin_workspace_size.restype = SZ
+        lib.vecchia_maxmin_workspace_size.argtypes = [I64]
+        lib.vecchia_maxmin_order.restype = ctypes.c_int
+        lib.vecchia_maxmin_order.argtypes = [P, I64, ctypes.c_uint64, P, P, SZ, P]
         lib.vecchia_knn_metric.restype = ctypes.c_int
         lib.vecchia_knn_metric.argtypes = [P, I64, I32, I32, P, P, SZ, P]
         lib.vecchia_knn_query.restype = ctypes.c_int
@@ -645,6 +649,27 @@ def vecchia_knn_query(locs, qlocs, m: int, metric: int = EUCLIDEAN, out=None, ws
     return out
 
 
+def vecchia_maxmin_order(locs, seed: int = 0, out=None, ws=None, stream=None):
+    """Approximate maxmin permutation (int64 [n]): rounds of per-cell elections over finer and finer
+    grids, each round in hashed-index order.  Synchronises the stream once per round."""
+    if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
+        raise ValueError("locs must be float64 [n][2]")
+    _dev_check(locs)
+    n = locs.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=locs.device)
+    if tuple(out.shape) != (n,) or out.dtype != torch.int64:
+        raise ValueError("out must be int64 [n]")
+    _dev_check(out)
+    need = int(_load().vecchia_maxmin_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
+    rc = _load().vecchia_maxmin_order(_ptr(locs), n, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(out),
+                                      _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "vecchia_maxmin_order")
+    return out
+
+
 def vecchia_morton_order(locs, out=None, ws=None, stream=None):
     """Morton (Z-order) permutation of the points: int64 [n], ties by index."""
     if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
@@ -739,8 +764,8 @@ def vecchia_dense_logdet(A, z=None, stream=None):
 def kl_curve(locs, ms, nu: float, theta, ordering: str = "random", seed: int = 0, stream=None) -> dict:
     """KL divergence of Eq. (9) against the conditioning size, for one ordering of the points.
 
-    ordering: "random" (a seeded permutation), "morton" (vecchia_morton_order) or
-    "given" (as passed).  The exact log-likelihood is computed once; each m
+    ordering: "random" (a seeded permutation), "morton" (vecchia_morton_order),
+    "maxmin" (vecchia_maxmin_order) or "given" (as passed).  The exact log-likelihood is computed once; each m
     takes GPU conditioning sets and one Vecchia evaluation at y = 0.
     Returns {"ordering", "exact", "exact_seconds", "kl": {m: KL}}.
     """
@@ -750,6 +775,8 @@ def kl_curve(locs, ms, nu: float, theta, ordering: str = "random", seed: int = 0
         locs = locs[torch.randperm(n, generator=g).to(locs.device)].contiguous()
     elif ordering == "morton":
         locs = locs[vecchia_morton_order(locs, stream=stream)].contiguous()
+    elif ordering == "maxmin":
+        locs = locs[vecchia_maxmin_order(locs, seed=seed, stream=stream)].contiguous()
     elif ordering != "given":
         raise ValueError(f"unknown ordering {ordering!r}")
     t0 = time.perf_counter()

@@ -407,6 +407,104 @@ __global__ void morton_code_kernel(const double *__restrict__ locs, int64_t n, c
     val[i] = (int32_t)i;
 }
 
+// ---- approximate maxmin ordering ---------------------------------------------
+//
+// Rounds of elections over grids of G x G square cells (G = 2^min(r, Lmax))
+// on the square box of side w = the larger side of the bounding box: each
+// cell elects its unselected point nearest the cell centre (ties by index);
+// a round's points follow the earlier rounds in ascending mix64(seed ^ i).
+// The decisions use the same rounded operations as their definition (no
+// contraction), so the permutation is exact.
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ int64_t maxmin_cell(double v, double v0, double w, int64_t G) {
+    double f = floor((v - v0) / w * (double)G);
+    f = (f >= 0.0) ? f : 0.0;  // negative or NaN: cell 0, so every index stays in range
+    f = f > (double)(G - 1) ? (double)(G - 1) : f;
+    return (int64_t)f;
+}
+
+// cell index and squared distance to the cell centre of point i
+__device__ __forceinline__ void maxmin_pos(const double *__restrict__ locs, int64_t i, const GridParams &p, double w,
+                                           int64_t G, int64_t &c, double &d) {
+    const double x = locs[2 * i], y = locs[2 * i + 1];
+    const int64_t cx = maxmin_cell(x, p.x0, w, G), cy = maxmin_cell(y, p.y0, w, G);
+    const double dx = x - (p.x0 + ((double)cx + 0.5) * w / (double)G);
+    const double dy = y - (p.y0 + ((double)cy + 0.5) * w / (double)G);
+    d = dx * dx + dy * dy;
+    c = cy * G + cx;
+}
+#pragma clang fp contract(on)
+
+__device__ __forceinline__ double maxmin_side(const GridParams &p) {
+    const double w = fmax(p.xmax - p.x0, p.ymax - p.y0);
+    return (w > 0.0) ? w : 1.0;
+}
+
+__global__ void fill_u64_kernel(uint64_t *__restrict__ a, int64_t count, uint64_t v) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        a[t] = v;
+}
+
+// phase 1: the least squared distance of each cell (non-negative doubles
+// order as their bit patterns)
+__global__ void maxmin_dist_kernel(const double *__restrict__ locs, int64_t n, const GridParams *__restrict__ gp,
+                                   int64_t G, const int32_t *__restrict__ sel, unsigned long long *__restrict__ cd) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || sel[i]) return;
+    const GridParams p = *gp;
+    int64_t c;
+    double d;
+    maxmin_pos(locs, i, p, maxmin_side(p), G, c, d);
+    atomicMin(cd + c, (unsigned long long)__double_as_longlong(d));
+}
+
+// phase 2: the least index at that distance
+__global__ void maxmin_index_kernel(const double *__restrict__ locs, int64_t n, const GridParams *__restrict__ gp,
+                                    int64_t G, const int32_t *__restrict__ sel,
+                                    const unsigned long long *__restrict__ cd, int32_t *__restrict__ ci) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || sel[i]) return;
+    const GridParams p = *gp;
+    int64_t c;
+    double d;
+    maxmin_pos(locs, i, p, maxmin_side(p), G, c, d);
+    if ((unsigned long long)__double_as_longlong(d) == cd[c]) atomicMin(ci + c, (int32_t)i);
+}
+
+// phase 3: elected points (all unselected ones when G == 0) join the round's list
+__global__ void maxmin_elect_kernel(const double *__restrict__ locs, int64_t n, const GridParams *__restrict__ gp,
+                                    int64_t G, int32_t *__restrict__ sel, const int32_t *__restrict__ ci,
+                                    uint64_t seed, uint64_t *__restrict__ key, int32_t *__restrict__ val,
+                                    int32_t *__restrict__ count) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || sel[i]) return;
+    bool elected = true;
+    if (G > 0) {
+        const GridParams p = *gp;
+        int64_t c;
+        double d;
+        maxmin_pos(locs, i, p, maxmin_side(p), G, c, d);
+        elected = ci[c] == (int32_t)i;
+    }
+    if (!elected) return;
+    sel[i] = 1;
+    const int32_t slot = atomicAdd(count, 1);
+    key[slot] = mix64(seed ^ (uint64_t)i);
+    val[slot] = (int32_t)i;
+}
+
+__global__ void append_kernel(const int32_t *__restrict__ v, int64_t cnt, int64_t *__restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < cnt) out[t] = v[t];
+}
+
 __global__ void widen_kernel(const int32_t *__restrict__ v, int64_t n, int64_t *__restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) out[i] = v[i];
@@ -469,6 +567,43 @@ MortonLayout morton_layout(int64_t n) {
     L.sval = o;   o += align256(sizeof(int32_t) * nn);
     size_t sort_bytes = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)nn);
+    L.temp_bytes = sort_bytes;
+    L.temp = o;   o += align256(sort_bytes);
+    L.total = o;
+    return L;
+}
+
+// Lmax: the least L >= 0 with 4^L >= n, plus 1, at most 15
+int maxmin_levels(int64_t n) {
+    int l = 0;
+    while (l < 14 && ((int64_t)1 << (2 * l)) < n) ++l;
+    return l + 1;
+}
+
+struct MaxminLayout {
+    size_t part, params, sel, cd, ci, key, val, skey, sval, count, temp, total, temp_bytes;
+    int64_t cells;
+};
+
+MaxminLayout maxmin_layout(int64_t n) {
+    MaxminLayout L{};
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const int64_t G = (int64_t)1 << maxmin_levels(n);
+    L.cells = G * G;
+    size_t o = 0;
+    L.part = o;   o += align256(sizeof(double) * 4 * kBoxBlocks);
+    L.params = o; o += align256(sizeof(GridParams));
+    L.sel = o;    o += align256(sizeof(int32_t) * nn);
+    L.cd = o;     o += align256(sizeof(uint64_t) * (size_t)L.cells);
+    L.ci = o;     o += align256(sizeof(int32_t) * (size_t)L.cells);
+    L.key = o;    o += align256(sizeof(uint64_t) * nn);
+    L.val = o;    o += align256(sizeof(int32_t) * nn);
+    L.skey = o;   o += align256(sizeof(uint64_t) * nn);
+    L.sval = o;   o += align256(sizeof(int32_t) * nn);
+    L.count = o;  o += 256;
+    size_t sort_bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
                                              (const int32_t *)nullptr, (int32_t *)nullptr, (int)nn);
     L.temp_bytes = sort_bytes;
     L.temp = o;   o += align256(sort_bytes);
@@ -584,5 +719,63 @@ extern "C" int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm
     if (hipcub::DeviceRadixSort::SortPairs(base + L.temp, tb, key, skey, val, sval, (int)n, 0, 32, s) != hipSuccess)
         return VECCHIA_EHIP;
     hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, sval, n, perm);
+    return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+}
+
+extern "C" size_t vecchia_maxmin_workspace_size(int64_t n) { return maxmin_layout(n < 0 ? 0 : n).total; }
+
+extern "C" int vecchia_maxmin_order(const double *locs, int64_t n, uint64_t seed, int64_t *perm, void *ws,
+                                    size_t ws_bytes, void *stream) {
+    if (n < 0 || n > INT32_MAX) return VECCHIA_EINVAL;
+    if (n == 0) return VECCHIA_OK;
+    if (!locs || !perm) return VECCHIA_EINVAL;
+    const MaxminLayout L = maxmin_layout(n);
+    if (!ws || ws_bytes < L.total) return VECCHIA_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *part = (double *)(base + L.part);
+    GridParams *gp = (GridParams *)(base + L.params);
+    int32_t *sel = (int32_t *)(base + L.sel);
+    unsigned long long *cd = (unsigned long long *)(base + L.cd);
+    int32_t *ci = (int32_t *)(base + L.ci);
+    uint64_t *key = (uint64_t *)(base + L.key), *skey = (uint64_t *)(base + L.skey);
+    int32_t *val = (int32_t *)(base + L.val), *sval = (int32_t *)(base + L.sval);
+    int32_t *count = (int32_t *)(base + L.count);
+    const int lmax = maxmin_levels(n);
+    const int nb = blocks_for(n, 256);
+    hipLaunchKernelGGL(box_partial_kernel, dim3(kBoxBlocks), dim3(256), 0, s, locs, n, part);
+    hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(kBoxBlocks), 0, s, part, 0, gp);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(nb, 4096)), dim3(256), 0, s, sel, n, 0);
+    int64_t done = 0;
+    for (int r = 0; done < n; ++r) {
+        const bool last = r >= lmax + 33;
+        const int64_t G = last ? 0 : (int64_t)1 << std::min(r, lmax);
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, count, 1, 0);
+        if (!last) {
+            const int64_t cells = G * G;
+            const int cb = std::min(blocks_for(cells, 256), 4096);
+            hipLaunchKernelGGL(fill_u64_kernel, dim3(cb), dim3(256), 0, s, (uint64_t *)cd, cells, ~(uint64_t)0);
+            hipLaunchKernelGGL(fill_int_kernel, dim3(cb), dim3(256), 0, s, ci, cells, INT32_MAX);
+            hipLaunchKernelGGL(maxmin_dist_kernel, dim3(nb), dim3(256), 0, s, locs, n, (const GridParams *)gp, G,
+                               (const int32_t *)sel, cd);
+            hipLaunchKernelGGL(maxmin_index_kernel, dim3(nb), dim3(256), 0, s, locs, n, (const GridParams *)gp, G,
+                               (const int32_t *)sel, (const unsigned long long *)cd, ci);
+        }
+        hipLaunchKernelGGL(maxmin_elect_kernel, dim3(nb), dim3(256), 0, s, locs, n, (const GridParams *)gp, G, sel,
+                           (const int32_t *)ci, seed, key, val, count);
+        if (hipGetLastError() != hipSuccess) return VECCHIA_EHIP;
+        int32_t cnt = 0;
+        if (hipMemcpyAsync(&cnt, count, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return VECCHIA_EHIP;
+        if (cnt <= 0 || done + cnt > n) return VECCHIA_EHIP;  // every round elects at least one point
+        size_t tb = L.temp_bytes;
+        if (hipcub::DeviceRadixSort::SortPairs(base + L.temp, tb, key, skey, val, sval, cnt, 0, 64, s) !=
+            hipSuccess)
+            return VECCHIA_EHIP;
+        hipLaunchKernelGGL(append_kernel, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, (const int32_t *)sval,
+                           (int64_t)cnt, perm + done);
+        done += cnt;
+    }
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }

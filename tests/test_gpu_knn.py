@@ -104,3 +104,27 @@ def test_morton_order(v, n):
     perm = v.vecchia_morton_order(torch.from_numpy(locs).cuda())
     torch.cuda.synchronize()
     np.testing.assert_array_equal(perm.cpu().numpy(), oracle.morton_order(locs))
+
+
+@pytest.mark.parametrize("case", ["uniform3000", "uniform50000", "lattice", "duplicates", "clusters", "one", "seven"])
+def test_maxmin_order(v, case):
+    import torch
+    rng = np.random.default_rng(1700)
+    if case.startswith("uniform"):
+        locs = rng.uniform(size=(int(case[7:]), 2))
+    elif case == "lattice":       # exact distance ties to the cell centres
+        g = 64
+        locs = np.stack(np.meshgrid(np.arange(g), np.arange(g)), -1).reshape(-1, 2).astype(np.float64)
+        locs = locs[rng.permutation(len(locs))]
+    elif case == "duplicates":
+        locs = np.repeat(rng.uniform(size=(40, 2)), 25, axis=0)[rng.permutation(1000)]
+    elif case == "clusters":
+        c = rng.uniform(size=(5, 2))
+        locs = c[rng.integers(0, 5, 20000)] + rng.normal(0, 1e-4, size=(20000, 2))
+    else:
+        locs = rng.uniform(size=(1 if case == "one" else 7, 2))
+    print(case, len(locs), flush=True)
+    for seed in (0, 12345):
+        got = v.vecchia_maxmin_order(torch.from_numpy(locs).cuda(), seed=seed)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.maxmin_order(locs, seed))

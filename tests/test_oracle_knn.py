@@ -128,3 +128,42 @@ def test_kl_is_zero_for_full_sets_and_decreases_with_m():
     assert all(a >= b for a, b in zip(kls, kls[1:]))  # nested nearest-neighbour sets (Eq. (9) >= 0, monotone)
     full = oracle.kl_divergence(locs, wl.nearest_previous_neighbours(locs, n - 1), n - 1, 1.5, theta)
     assert abs(full) <= 1e-9 * n
+
+
+# ---- approximate maxmin ordering -------------------------------------------------------------
+def test_maxmin_hand_worked():
+    # box [0, 1]^2: round 0 elects the point nearest (0.5, 0.5); round 1 one point per quadrant (the
+    # lower-left quadrant's is the one nearest (0.25, 0.25)); round 2 the rest
+    pts = np.array([[0, 0], [1, 0], [0, 1], [1, 1], [0.5, 0.5], [0.26, 0.24]], dtype=float)
+    for seed in (0, 7, 2 ** 63 + 5):
+        p = oracle.maxmin_order(pts, seed)
+        assert p[0] == 4 and set(p[1:5]) == {1, 2, 3, 5} and p[5] == 0
+
+
+def test_maxmin_rounds_are_seed_independent_and_spread():
+    rng = np.random.default_rng(1600)
+    x = rng.uniform(size=(2000, 2))
+    a, b = oracle.maxmin_order(x, 1), oracle.maxmin_order(x, 2)
+    assert sorted(a) == list(range(2000)) and sorted(b) == list(range(2000))
+    w = (x.max(0) - x.min(0)).max()      # side of the square box on the lower-left corner
+    centre = np.argmin(((x - (x.min(0) + 0.5 * w)) ** 2).sum(1))
+    assert a[0] == b[0] == centre
+    for level, end in ((1, 5), (2, 21), (3, 85)):
+        assert set(a[:end]) == set(b[:end])
+        g = 2 ** level
+        start = end - g * g
+        cells = np.minimum(np.floor((x[a[start:end]] - x.min(0)) / w * g), g - 1)
+        assert len({(int(cx), int(cy)) for cx, cy in cells}) == g * g
+    # maxmin character: the first points are far more spread than a random subset of the same size
+    def min_gap(p):
+        d = np.sqrt(((p[:, None, :] - p[None, :, :]) ** 2).sum(-1))
+        return d[np.triu_indices(len(p), 1)].min()
+    assert min_gap(x[a[:85]]) > 4 * min_gap(x[rng.permutation(2000)[:85]])
+
+
+def test_maxmin_coincident_points():
+    pts = np.full((100, 2), 0.3)
+    p = oracle.maxmin_order(pts, 11)
+    # lmax = 5 for n = 100: 38 rounds elect one point each (lowest index first), the rest follow by key
+    np.testing.assert_array_equal(p[:38], np.arange(38))
+    assert sorted(p) == list(range(100))
