@@ -452,17 +452,39 @@ __global__ void fill_u64_kernel(uint64_t *__restrict__ a, int64_t count, uint64_
         a[t] = v;
 }
 
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, kWaveK);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 // phase 1: the least squared distance of each cell (non-negative doubles
-// order as their bit patterns)
+// order as their bit patterns).  On the coarse grids (at most 16 cells) every
+// wavefront first takes the minimum per cell, so a cell sees one atomic per
+// wavefront instead of one per point.
 __global__ void maxmin_dist_kernel(const double *__restrict__ locs, int64_t n, const GridParams *__restrict__ gp,
                                    int64_t G, const int32_t *__restrict__ sel, unsigned long long *__restrict__ cd) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n || sel[i]) return;
-    const GridParams p = *gp;
-    int64_t c;
-    double d;
-    maxmin_pos(locs, i, p, maxmin_side(p), G, c, d);
-    atomicMin(cd + c, (unsigned long long)__double_as_longlong(d));
+    const bool active = i < n && !sel[i];
+    int64_t c = 0;
+    double d = 0.0;
+    if (active) {
+        const GridParams p = *gp;
+        maxmin_pos(locs, i, p, maxmin_side(p), G, c, d);
+    }
+    const unsigned long long key = (unsigned long long)__double_as_longlong(d);
+    if (G * G <= 16) {  // uniform over the launch
+        const int lane = threadIdx.x % kWaveK;
+        for (int64_t cc = 0; cc < G * G; ++cc) {
+            const unsigned long long v = wave_min_u64((active && c == cc) ? key : ~0ull);
+            if (lane == 0 && v != ~0ull) atomicMin(cd + cc, v);
+        }
+    } else if (active) {
+        atomicMin(cd + c, key);
+    }
 }
 
 // phase 2: the least index at that distance
