@@ -313,3 +313,48 @@ def kl_divergence(locs, nbr, m: int, nu: float, theta, threads: int = 0) -> floa
     """Eq. (9): exact minus Vecchia log-likelihood at y = 0."""
     n = np.asarray(locs).shape[0]
     return exact_loglik(locs, None, nu, theta) - loglik(locs, np.zeros(n), nbr, m, nu, theta, threads=threads)
+
+
+def term_mp(locs, z, nbr, m: int, nu: float, theta, i: int, dps: int = 50) -> float:
+    """l_i of Eq. (7) in arbitrary precision (mpmath, `dps` decimal digits), for adjudicating rounding
+    differences between two FP64 evaluations of an ill-conditioned conditional.  The FP64 inputs are
+    taken as exact; the covariance (Matern closed forms, nugget on equal indices), the Cholesky factor,
+    the two forward solves and the univariate term follow the same steps as the C oracle."""
+    import mpmath as mp
+
+    locs = np.asarray(locs, dtype=np.float64)
+    with mp.workdps(dps):
+        s2, beta, tau2 = (mp.mpf(float(t)) for t in theta)
+        k = int(min(i, m))
+        J = [int(j) for j in np.asarray(nbr)[i, :k]]
+
+        def cov(a, b):
+            d = mp.sqrt((mp.mpf(locs[a, 0]) - mp.mpf(locs[b, 0])) ** 2 + (mp.mpf(locs[a, 1]) - mp.mpf(locs[b, 1])) ** 2)
+            r = d / beta
+            e = mp.exp(-r)
+            if nu == 0.5:
+                return s2 * e
+            if nu == 1.5:
+                return s2 * (1 + r) * e
+            return s2 * (1 + r + r * r / 3) * e
+
+        S = mp.matrix(k, k)
+        for a in range(k):
+            for b in range(a + 1):
+                S[a, b] = S[b, a] = cov(J[a], J[b]) + (tau2 if a == b else 0)
+        v = [cov(J[a], i) for a in range(k)]
+        y = [mp.mpf(float(z[j])) for j in J]
+        vp, yp = [], []
+        if k:
+            L = mp.cholesky(S)
+            for r_ in range(k):
+                av, ay = v[r_], y[r_]
+                for q in range(r_):
+                    av -= L[r_, q] * vp[q]
+                    ay -= L[r_, q] * yp[q]
+                vp.append(av / L[r_, r_])
+                yp.append(ay / L[r_, r_])
+        mu = mp.fsum(a * b for a, b in zip(vp, yp))
+        c = s2 + tau2 - mp.fsum(a * a for a in vp)
+        res = mp.mpf(float(z[i])) - mu
+        return float(-(mp.log(2 * mp.pi) + mp.log(c) + res * res / c) / 2)

@@ -313,3 +313,25 @@ def test_invalid_arguments():
     bad[7, 0] = 7  # not a previous point
     with pytest.raises(oracle.OracleError):
         oracle.loglik(locs, z, bad, 5, 0.5, (1.0, 0.1, 0.0))
+
+
+def test_arbitrary_precision_term_agrees_with_the_fp64_oracle():
+    """The mpmath evaluation used to adjudicate rounding: equal to the FP64 oracle on well-conditioned
+    conditionals, stable when the precision grows, and the more accurate of the two on a near-singular one."""
+    import workloads as wl
+    rng = np.random.default_rng(1900)
+    f = wl.small_field(rng, 400, 12, 1.5, (1.0, 0.05, 1e-2))
+    theta = (1.0, 0.05, 1e-2)
+    rows = [0, 1, 5, 12, 13, 200, 399]
+    fp = oracle.terms(f.locs, f.z, f.nbr, f.m, 1.5, theta, idx=rows)
+    for r, t in zip(rows, fp):
+        mp50 = oracle.term_mp(f.locs, f.z, f.nbr, f.m, 1.5, theta, r, dps=50)
+        assert abs(mp50 - t) <= 1e-12 * max(1.0, abs(t))
+        assert oracle.term_mp(f.locs, f.z, f.nbr, f.m, 1.5, theta, r, dps=80) == mp50
+    # a conditional made nearly singular (a tiny nugget, smooth kernel, long range): FP64 loses digits,
+    # the 50-digit value does not move at 80 digits
+    g = wl.small_field(rng, 300, 30, 2.5, (1.0, 0.4, 1e-9))
+    th = (1.0, 0.4, 1e-9)
+    a = oracle.term_mp(g.locs, g.z, g.nbr, g.m, 2.5, th, 299, dps=50)
+    b = oracle.term_mp(g.locs, g.z, g.nbr, g.m, 2.5, th, 299, dps=80)
+    assert abs(a - b) <= 1e-14 * abs(b)
