@@ -43,29 +43,6 @@ __host__ __device__ constexpr bool kc_gcd(int KC) { return (KC >> 2) != 0; }
 constexpr double kEarthRadiusKm = 6371.0;
 constexpr double kDeg2Rad = 0.017453292519943295769236907684886;
 
-// Great-circle distance in km between (lon, lat) points a and b in degrees,
-// given cos(lat) of each: hav(d / R) = hav(dlat) + cos lat_a cos lat_b hav(dlon)
-// with hav(t) = sin^2(t / 2), differences taken in degrees first.  Coincident
-// points give exactly 0.
-__device__ __forceinline__ double gcd_km(double lona, double lata, double ca, double lonb, double latb, double cb) {
-    const double s1 = sin(0.5 * ((lata - latb) * kDeg2Rad));
-    const double s2 = sin(0.5 * ((lona - lonb) * kDeg2Rad));
-    const double h = fmin(fma(s1, s1, (ca * cb) * (s2 * s2)), 1.0);
-    return (2.0 * kEarthRadiusKm) * asin(sqrt(h));
-}
-
-// Scaled distance r fed to the closed forms: d / beta (Matern) or
-// d^alpha / beta (power exponential; alpha = 1 and 2 without pow).
-template <int KC>
-__device__ __forceinline__ double cov_scaled(double d, const Params &P) {
-    if constexpr (kc_family(KC) == 3) {
-        const double da = (P.alpha == 1.0) ? d : (P.alpha == 2.0) ? d * d : pow(d, P.alpha);
-        return da * P.inv_beta;
-    } else {
-        return d * P.inv_beta;
-    }
-}
-
 // e^{-r} for r >= 0.  Range reduction x = -r = k ln2 + f with |f| <= ln2/2
 // (ln2 split into a head with trailing zero bits and a tail, so k*ln2_head is
 // exact), e^f by its Taylor polynomial of degree 13 (truncation below 6e-18
@@ -151,6 +128,76 @@ __device__ __forceinline__ double sqrt_pos(double s) {
     return fma(d, h, g);
 }
 
+// sin x.  Neighbouring points give half-angle differences far below 0.25
+// rad, where the Taylor polynomial to x^13 is used (truncation below 1e-21
+// relative, Horner in x^2, one rounding at the end); larger arguments take
+// the library sine.
+__device__ __forceinline__ double sin_short(double x) {
+    if (fabs(x) <= 0.25) {
+        const double x2 = x * x;
+        double q = 1.0 / 6227020800.0;   // 1/13!
+        q = fma(q, x2, -1.0 / 39916800.0);  // -1/11!
+        q = fma(q, x2, 1.0 / 362880.0);     // 1/9!
+        q = fma(q, x2, -1.0 / 5040.0);      // -1/7!
+        q = fma(q, x2, 1.0 / 120.0);        // 1/5!
+        q = fma(q, x2, -1.0 / 6.0);         // -1/3!
+        return fma(x * x2, q, x);
+    }
+    return sin(x);
+}
+
+// asin(sqrt(h)) for 0 <= h <= 1.  For h <= 0.01 (great-circle distances up
+// to about 1270 km) the series asin s = s (1 + sum_n c_n s^2n), c_n =
+// (2n)! / (4^n (n!)^2 (2n + 1)), to n = 8 (truncation below 2e-18
+// relative); otherwise the library asin.
+__device__ __forceinline__ double asin_sqrt(double h) {
+    const double s = sqrt(h);
+    if (h <= 0.01) {
+        double p = 6435.0 / 557056.0;
+        p = fma(p, h, 143.0 / 10240.0);
+        p = fma(p, h, 231.0 / 13312.0);
+        p = fma(p, h, 63.0 / 2816.0);
+        p = fma(p, h, 35.0 / 1152.0);
+        p = fma(p, h, 5.0 / 112.0);
+        p = fma(p, h, 3.0 / 40.0);
+        p = fma(p, h, 1.0 / 6.0);
+        return fma(s * h, p, s);
+    }
+    return asin(s);
+}
+
+// Great-circle distance in km between (lon, lat) points a and b in degrees,
+// given cos(lat) of each: hav(d / R) = hav(dlat) + cos lat_a cos lat_b hav(dlon)
+// with hav(t) = sin^2(t / 2), differences taken in degrees first.  Coincident
+// points give exactly 0.
+__device__ __forceinline__ double gcd_km(double lona, double lata, double ca, double lonb, double latb, double cb) {
+    const double s1 = sin_short(0.5 * ((lata - latb) * kDeg2Rad));
+    const double s2 = sin_short(0.5 * ((lona - lonb) * kDeg2Rad));
+    const double h = fmin(fma(s1, s1, (ca * cb) * (s2 * s2)), 1.0);
+    return (2.0 * kEarthRadiusKm) * asin_sqrt(h);
+}
+
+// Scaled distance r fed to the closed forms: d / beta (Matern) or
+// d^alpha / beta (power exponential; alpha = 1 and 2 without the
+// exponential, otherwise e^(alpha ln d) with the table exponential, and 0
+// for d = 0).
+template <int KC>
+__device__ __forceinline__ double cov_scaled(double d, const Params &P, const double *tab) {
+    if constexpr (kc_family(KC) == 3) {
+        double da;
+        if (P.alpha == 1.0) {
+            da = d;
+        } else if (P.alpha == 2.0) {
+            da = d * d;
+        } else {
+            da = (d > 0.0) ? exp_neg_tab(-(P.alpha * log(d)), tab) : 0.0;
+        }
+        return da * P.inv_beta;
+    } else {
+        return d * P.inv_beta;
+    }
+}
+
 // Covariance C(d) and, with WITH_D, its beta-derivative for points a and b
 // (cos of the latitudes in ca, cb for the great-circle codes), using
 // exp_neg_tab.  With r the scaled distance, the Matern forms are sigma2 m(r)
@@ -162,10 +209,10 @@ __device__ __forceinline__ void cov_pair(double xa, double ya, double ca, double
                                          const Params &P, double s2b, const double *tab, double &c, double &db) {
     double r;
     if constexpr (kc_gcd(KC)) {
-        r = cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P);
+        r = cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P, tab);
     } else {
         const double dx = xa - xb, dy = ya - yb;
-        r = cov_scaled<KC>(sqrt_pos(fma(dx, dx, dy * dy)), P);
+        r = cov_scaled<KC>(sqrt_pos(fma(dx, dx, dy * dy)), P, tab);
     }
     const double e = exp_neg_tab(r, tab);
     constexpr int F = kc_family(KC);
@@ -234,14 +281,18 @@ __device__ __forceinline__ double dist2d(double ax, double ay, double bx, double
     return sqrt_dist(fma(dx, dx, dy * dy));
 }
 
+// 2^(j/64) as (hi, lo) pairs in global memory, for code that does not stage
+// the table in LDS.
+__device__ __forceinline__ const double *exp_table_global() { return reinterpret_cast<const double *>(kExp2Frac64); }
+
 // Scaled distance of a pair under covariance code KC (the unblocked kernel's form).
 template <int KC>
 __device__ __forceinline__ double cov_r(double xa, double ya, double ca, double xb, double yb, double cb,
                                         const Params &P) {
     if constexpr (kc_gcd(KC)) {
-        return cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P);
+        return cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P, exp_table_global());
     } else {
-        return cov_scaled<KC>(dist2d(xa, ya, xb, yb), P);
+        return cov_scaled<KC>(dist2d(xa, ya, xb, yb), P, exp_table_global());
     }
 }
 
