@@ -15,7 +15,8 @@
 // index) is total and every candidate that could beat the m-th best is seen.
 // Prediction points search all observed points the same way.  Great-circle
 // sets (points as (longitude, latitude) in degrees) rank candidates by the
-// haversine value and scan every candidate.
+// haversine value on the same grid, with a haversine lower bound for the
+// unscanned rings.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <stdint.h>
@@ -172,12 +173,15 @@ __global__ void cell_kernel(const double *__restrict__ locs, int64_t n, const Gr
     atomicAdd(count + c, 1);
 }
 
+// Points in cell order; with clat (great-circle sets) also their cos(latitude).
 __global__ void gather_sorted_kernel(const double *__restrict__ locs, int64_t n, const int32_t *__restrict__ idx,
-                                     double2 *__restrict__ sxy) {
+                                     const double *__restrict__ clat, double2 *__restrict__ sxy,
+                                     double *__restrict__ sclat) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t j = idx[p];
     sxy[p] = double2{locs[2 * j], locs[2 * j + 1]};
+    if (clat) sclat[p] = clat[j];
 }
 
 // ---- queries ----------------------------------------------------------------
@@ -266,10 +270,20 @@ __device__ __forceinline__ void ring_cell(int r, int e, int &dx, int &dy) {
 // Query i (0 <= i < nq): its candidates are the points j < lim of locs, with
 // lim = i for conditioning sets (qlocs == NULL, query point locs[i]) and
 // lim = n for prediction points (query point qlocs[i]).
+//
+// GCD: points are (longitude, latitude) degrees on the same grid, keys are
+// hav_key values (clat / sclat hold cos(latitude) in input / cell order).
+// An unscanned point lies at least a = r h degrees away in longitude or in
+// latitude; with both spans within 180 degrees its haversine value is at
+// least sin^2(a / 2) min(1, cos lat_q cos lat_min), cos lat_min the least
+// cosine over the points' latitudes (all in [-90, 90]).  A query whose
+// longitude span exceeds 180 degrees scans every cell.
+template <bool GCD>
 __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
     const double *__restrict__ locs, int64_t n, const double *__restrict__ qlocs, int64_t nq, int32_t m,
     const double2 *__restrict__ sxy, const int32_t *__restrict__ sidx, const int32_t *__restrict__ cstart,
-    const GridParams *__restrict__ gp, int g, int32_t *__restrict__ nbr) {
+    const GridParams *__restrict__ gp, int g, const double *__restrict__ clat, const double *__restrict__ sclat,
+    int32_t *__restrict__ nbr) {
     __shared__ double sbd[kKnnWaves][kKnnCap];
     __shared__ int32_t sbj[kKnnWaves][kKnnCap];
     const int w = threadIdx.x / kWaveK, lane = threadIdx.x % kWaveK;
@@ -284,19 +298,31 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
     }
     const double *qp = qlocs ? qlocs + 2 * i : locs + 2 * i;
     const double qx = qp[0], qy = qp[1];
+    double cq = 0.0;
+    if constexpr (GCD) cq = qlocs ? cos(qy * kDeg2Rad) : clat[i];
     TopK top{sbd[w], sbj[w], 0, k, lane, INFINITY, INT32_MAX};
 
     if (lim <= kBruteMax) {
         for (int64_t base = 0; base < lim; base += kWaveK) {
             const int64_t j = base + lane;
             const bool valid = j < lim;
-            const double d = valid ? sqdist(qx, qy, locs[2 * j], locs[2 * j + 1]) : 0.0;
+            double d = 0.0;
+            if (valid) {
+                if constexpr (GCD) d = hav_key(qx, qy, cq, locs[2 * j], locs[2 * j + 1], clat[j]);
+                else d = sqdist(qx, qy, locs[2 * j], locs[2 * j + 1]);
+            }
             top.consider(valid, d, (int32_t)j);
         }
     } else {
         const GridParams p = *gp;
         const int cx = cell_coord(qx, p.x0, p.inv_h, g);
         const int cy = cell_coord(qy, p.y0, p.inv_h, g);
+        double hfac = 0.0;  // GCD: min(1, cos lat_q cos lat_min), 0 when no bound applies
+        if constexpr (GCD) {
+            const double span = fmax(p.xmax, qx) - fmin(p.x0, qx);
+            const double cmin = fmin(cos(p.y0 * kDeg2Rad), cos(p.ymax * kDeg2Rad));
+            hfac = (span <= 180.0) ? fmin(1.0, cq * cmin) : 0.0;
+        }
         for (int r = 0;; ++r) {
             const int ncell = (r == 0) ? 1 : 8 * r;
             for (int e0 = 0; e0 < ncell; e0 += kWaveK) {
@@ -315,7 +341,8 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
                     int32_t j = 0;
                     if (active) {
                         const double2 s = sxy[pp];
-                        d = sqdist(qx, qy, s.x, s.y);
+                        if constexpr (GCD) d = hav_key(qx, qy, cq, s.x, s.y, sclat[pp]);
+                        else d = sqdist(qx, qy, s.x, s.y);
                         j = sidx[pp];
                         ++pp;
                     }
@@ -327,10 +354,17 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
             if (top.c >= k) {
                 if (top.c > k) top.trim();
                 // every unscanned point lies at least r cells off in x or y:
-                // its distance exceeds r h up to the rounding of the binning,
+                // its offset exceeds r h up to the rounding of the binning,
                 // which the margins cover
                 const double dmin = (double)r * p.h * (1.0 - 1e-9) - 1e-12 * (double)g * p.h;
-                if (dmin > 0.0 && dmin * dmin > top.thr_d) break;
+                if constexpr (GCD) {
+                    if (dmin > 0.0 && hfac > 0.0) {
+                        const double sa = sin(0.5 * (fmin(dmin, 180.0) * kDeg2Rad));
+                        if ((sa * sa) * hfac * (1.0 - 1e-9) > top.thr_d) break;
+                    }
+                } else {
+                    if (dmin > 0.0 && dmin * dmin > top.thr_d) break;
+                }
             }
         }
     }
@@ -341,37 +375,6 @@ __global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_query_kernel(
 __global__ void cos_lat_kernel(const double *__restrict__ locs, int64_t n, double *__restrict__ clat) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) clat[i] = cos(locs[2 * i + 1] * kDeg2Rad);
-}
-
-// Great-circle sets by brute force: query i against every candidate j < lim
-// (lim as in knn_query_kernel), keys from hav_key with clat[j] = cos(lat_j).
-__global__ void __launch_bounds__(kKnnWaves *kWaveK) knn_gcd_kernel(
-    const double *__restrict__ locs, const double *__restrict__ clat, int64_t n, const double *__restrict__ qlocs,
-    int64_t nq, int32_t m, int32_t *__restrict__ nbr) {
-    __shared__ double sbd[kKnnWaves][kKnnCap];
-    __shared__ int32_t sbj[kKnnWaves][kKnnCap];
-    const int w = threadIdx.x / kWaveK, lane = threadIdx.x % kWaveK;
-    const int64_t i = blockIdx.x * (int64_t)kKnnWaves + w;
-    if (i >= nq) return;
-    const int64_t lim = qlocs ? n : i;
-    const int k = (int)(lim < m ? lim : m);
-    int32_t *out = nbr + i * (int64_t)m;
-    if (k == 0) {
-        for (int t = lane; t < m; t += kWaveK) out[t] = -1;
-        return;
-    }
-    const double *qp = qlocs ? qlocs + 2 * i : locs + 2 * i;
-    const double qlon = qp[0], qlat = qp[1];
-    const double cq = qlocs ? cos(qlat * kDeg2Rad) : clat[i];
-    TopK top{sbd[w], sbj[w], 0, k, lane, INFINITY, INT32_MAX};
-    for (int64_t base = 0; base < lim; base += kWaveK) {
-        const int64_t j = base + lane;
-        const bool valid = j < lim;
-        const double d = valid ? hav_key(qlon, qlat, cq, locs[2 * j], locs[2 * j + 1], clat[j]) : 0.0;
-        top.consider(valid, d, (int32_t)j);
-    }
-    top.trim();
-    for (int t = lane; t < m; t += kWaveK) out[t] = (t < top.c) ? top.bj[t] : -1;
 }
 
 // ---- Morton ordering --------------------------------------------------------
@@ -537,7 +540,7 @@ __global__ void widen_kernel(const int32_t *__restrict__ v, int64_t n, int64_t *
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct KnnLayout {
-    size_t part, params, key, val, skey, sval, count, cstart, sxy, clat, temp, total, temp_bytes;
+    size_t part, params, key, val, skey, sval, count, cstart, sxy, clat, sclat, temp, total, temp_bytes;
     int g;
     int64_t cells;
 };
@@ -567,6 +570,7 @@ KnnLayout knn_layout(int64_t n) {
     L.cstart = o; o += align256(sizeof(int32_t) * (size_t)(L.cells + 1));
     L.sxy = o;    o += align256(sizeof(double2) * nn);
     L.clat = o;   o += align256(sizeof(double) * nn);
+    L.sclat = o;  o += align256(sizeof(double) * nn);
     L.temp_bytes = knn_temp_bytes((int64_t)nn, L.cells);
     L.temp = o;   o += align256(L.temp_bytes);
     L.total = o;
@@ -653,22 +657,19 @@ int knn_run(const double *locs, int64_t n, const double *qlocs, int64_t nq, int3
             void *ws, size_t ws_bytes, hipStream_t s) {
     const KnnLayout L = knn_layout(n);
     if (!ws || ws_bytes < L.total) return VECCHIA_EWORKSPACE;
+    const bool gcd = metric == VECCHIA_GREAT_CIRCLE;
     char *base = (char *)ws;
-    if (metric == VECCHIA_GREAT_CIRCLE) {
-        double *clat = (double *)(base + L.clat);
-        if (n > 0) hipLaunchKernelGGL(cos_lat_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, clat);
-        hipLaunchKernelGGL(knn_gcd_kernel, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s, locs,
-                           (const double *)clat, n, qlocs, nq, m, nbr);
-        return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
-    }
     double *part = (double *)(base + L.part);
     GridParams *gp = (GridParams *)(base + L.params);
     int32_t *key = (int32_t *)(base + L.key), *val = (int32_t *)(base + L.val);
     int32_t *skey = (int32_t *)(base + L.skey), *sval = (int32_t *)(base + L.sval);
     int32_t *count = (int32_t *)(base + L.count), *cstart = (int32_t *)(base + L.cstart);
     double2 *sxy = (double2 *)(base + L.sxy);
+    double *clat = gcd ? (double *)(base + L.clat) : nullptr;
+    double *sclat = gcd ? (double *)(base + L.sclat) : nullptr;
     void *temp = base + L.temp;
     if (n > 0) {
+        if (gcd) hipLaunchKernelGGL(cos_lat_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, clat);
         hipLaunchKernelGGL(box_partial_kernel, dim3(kBoxBlocks), dim3(256), 0, s, locs, n, part);
         hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(kBoxBlocks), 0, s, part, L.g, gp);
         hipLaunchKernelGGL(fill_int_kernel, dim3(std::min(blocks_for(L.cells + 1, 256), 4096)), dim3(256), 0, s,
@@ -683,11 +684,19 @@ int knn_run(const double *locs, int64_t n, const double *qlocs, int64_t nq, int3
         tb = L.temp_bytes;
         if (hipcub::DeviceScan::ExclusiveSum(temp, tb, count, cstart, (int)(L.cells + 1), s) != hipSuccess)
             return VECCHIA_EHIP;
-        hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, sval, sxy);
+        hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, sval,
+                           (const double *)clat, sxy, sclat);
     }
-    hipLaunchKernelGGL(knn_query_kernel, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s, locs, n,
-                       qlocs, nq, m, (const double2 *)sxy, (const int32_t *)sval, (const int32_t *)cstart,
-                       (const GridParams *)gp, L.g, nbr);
+    if (gcd)
+        hipLaunchKernelGGL(knn_query_kernel<true>, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s,
+                           locs, n, qlocs, nq, m, (const double2 *)sxy, (const int32_t *)sval,
+                           (const int32_t *)cstart, (const GridParams *)gp, L.g, (const double *)clat,
+                           (const double *)sclat, nbr);
+    else
+        hipLaunchKernelGGL(knn_query_kernel<false>, dim3(blocks_for(nq, kKnnWaves)), dim3(kKnnWaves * kWaveK), 0, s,
+                           locs, n, qlocs, nq, m, (const double2 *)sxy, (const int32_t *)sval,
+                           (const int32_t *)cstart, (const GridParams *)gp, L.g, (const double *)nullptr,
+                           (const double *)nullptr, nbr);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
 

@@ -219,3 +219,31 @@ def test_query_sets_outside_the_box_and_errors(v):
     rc = v.library().vecchia_knn_query(ctypes.c_void_p(R.data_ptr()), 12000, ctypes.c_void_p(R.data_ptr()), 4, 5, 0,
                                        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(small.data_ptr()), 16, None)
     assert rc == 4  # VECCHIA_EWORKSPACE
+
+
+@pytest.mark.parametrize("region", ["mid", "polar", "antimeridian"])
+def test_great_circle_grid_search_matches_oracle(v, region):
+    """Beyond 8192 points the great-circle sets come from the grid with the haversine bound; near the
+    pole the bound is weak, across the antimeridian (longitude span above 180 degrees) every cell is
+    scanned.  Both kinds of sets against brute force."""
+    import torch
+    rng = np.random.default_rng(1450 + len(region))
+    n, nq, m = 30000, 1500, 40
+    if region == "mid":
+        locs, q = lonlat(rng, n), lonlat(rng, nq)
+    elif region == "polar":
+        locs = np.column_stack([rng.uniform(-180, 180, n), rng.uniform(80.0, 89.9, n)])
+        q = np.column_stack([rng.uniform(-180, 180, nq), rng.uniform(78.0, 89.9, nq)])
+    else:
+        lon = rng.uniform(170.0, 190.0, n)
+        locs = np.column_stack([np.where(lon > 180.0, lon - 360.0, lon), rng.uniform(-5, 5, n)])
+        lq = rng.uniform(170.0, 190.0, nq)
+        q = np.column_stack([np.where(lq > 180.0, lq - 360.0, lq), rng.uniform(-5, 5, nq)])
+    dev = torch.device("cuda:0")
+    L, Q = torch.from_numpy(locs).to(dev), torch.from_numpy(q).to(dev)
+    got = v.vecchia_knn(L, m, metric=1)
+    gq = v.vecchia_knn_query(L, Q, m, metric=1)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.arange(8150, 8300), rng.choice(n, 1500, replace=False)]))
+    np.testing.assert_array_equal(got.cpu().numpy()[rows], oracle.knn_rows(locs, m, rows=rows, metric=1, threads=16))
+    np.testing.assert_array_equal(gq.cpu().numpy(), oracle.knn_query(locs, q, m, metric=1, threads=16))
