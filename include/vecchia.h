@@ -347,10 +347,13 @@ int vecchia_knn(const double *locs, int64_t n, int32_t m, int32_t *nbr, void *ws
  * candidates by the haversine value sin^2(dlat/2) + cos lat_i cos lat_j
  * sin^2(dlon/2) (monotone in the great-circle distance of Sec. V-C, latitude
  * and longitude differences taken in degrees before conversion), ties by
- * index; every candidate is compared (O(n^2 / 2) work).  The haversine value
- * uses the device's sine and cosine, so keys equal to the last bits may order
- * differently from another library's.  Other arguments and returns as
- * vecchia_knn; an unknown metric is VECCHIA_EINVAL.
+ * index.  The search uses the grid of vecchia_knn over (longitude,
+ * latitude) with a lower bound of the haversine value for unscanned rings;
+ * latitudes must lie in [-90, 90], and a longitude span above 180 degrees
+ * makes every query scan all cells.  The haversine value uses the device's
+ * sine and cosine, so keys equal to the last bits may order differently
+ * from another library's.  Other arguments and returns as vecchia_knn; an
+ * unknown metric is VECCHIA_EINVAL.
  */
 int vecchia_knn_metric(const double *locs, int64_t n, int32_t m, int32_t metric, int32_t *nbr, void *ws,
                        size_t ws_bytes, void *stream);
@@ -361,8 +364,8 @@ int vecchia_knn_metric(const double *locs, int64_t n, int32_t m, int32_t metric,
  * candidates), ordered as vecchia_knn_metric orders them, -1 past min(n, m).
  *   locs   [dev] double[n][2];  qlocs [dev] double[nq][2];  nbr [dev] int32[nq][m]
  *   ws     [dev] at least vecchia_knn_workspace_size(n) bytes
- * Euclidean queries use the grid of vecchia_knn over locs (queries outside
- * its bounding box included), great-circle queries compare every point.
+ * Both metrics use the grid of vecchia_knn over locs (queries outside its
+ * bounding box included), as vecchia_knn_metric.
  * Asynchronous.  Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED
  * (m > VECCHIA_MAX_M), VECCHIA_EWORKSPACE or VECCHIA_EHIP.
  */
