@@ -42,14 +42,14 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # HBM traffic of the conditional kernel per launch on the default workload,
 # from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch) with --copy-probe: the probe's 512 MiB device copy reads
-# 262171.2 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
+# 262161.9 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
 # scale factors.  It describes the kernel sources it was measured on only, so
 # it is reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6a414fae7993a3fe4456452870acc74538352705a85fa3c6de141b23ab0e647c",
+    "sources_sha256": "9b04a2016e46a63ead8ae050718d42a767bcfce361c1e9979a6a3703d89b06a7",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 8461569.5625, "fetch_factor": 524288.0 / 262171.1875,
-    "write_kib_raw": 2612423.53125, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 8461162.5625, "fetch_factor": 524288.0 / 262161.875,
+    "write_kib_raw": 2613832.90625, "write_factor": 524288.0 / 524288.0,
 }
 
 
