@@ -429,16 +429,16 @@ def raise_on_status(status) -> None:
 
 # ------------------------------------------------------------------ autograd
 class VecchiaLogLik(torch.autograd.Function):
-    """l(theta) with the analytic adjoint; theta = (sigma2, beta, tau2) as a float64 device tensor [3]."""
+    """l(theta) with the analytic adjoint; theta = (sigma2, beta, tau2) as a float64 device tensor [3].
+    `model` is the Matern smoothness nu (a float) or a covariance model (family, metric, smoothness)."""
 
     @staticmethod
-    def forward(ctx, theta, locs, z, nbr, nu, m, check):
+    def forward(ctx, theta, locs, z, nbr, model, m, check):
         theta_c = theta.detach().contiguous()
+        cov = model if isinstance(model, (tuple, list, Cov)) else (MATERN, EUCLIDEAN, float(model))
+        out, grad, status = vecchia_loglik_cov(locs, z, nbr, m, cov, theta_c, with_grad=ctx.needs_input_grad[0])
         if ctx.needs_input_grad[0]:
-            out, grad, status = vecchia_loglik_grad(locs, z, nbr, m, nu, theta_c)
             ctx.save_for_backward(grad)
-        else:
-            out, status = vecchia_loglik(locs, z, nbr, m, nu, theta_c)
         if check:
             raise_on_status(status)
         return out.reshape(())
@@ -449,13 +449,15 @@ class VecchiaLogLik(torch.autograd.Function):
         return grad_out * grad, None, None, None, None, None, None
 
 
-def loglik(locs, z, nbr, theta, nu: float, m: int, check: bool = True):
-    """Differentiable Vecchia log-likelihood (0-d float64 tensor on the device).
+def loglik(locs, z, nbr, theta, nu: float, m: int, check: bool = True, cov=None):
+    """Differentiable Vecchia log-likelihood (0-d float64 tensor on the device), Matern with smoothness
+    nu on Euclidean distances, or the covariance model cov = (family, metric, smoothness) when given.
 
     check=True synchronises once to raise VecchiaNumericalError on a failed
     conditional; pass False inside captured graphs or tight loops and read the
     status yourself."""
-    return VecchiaLogLik.apply(theta, locs, z, nbr, float(nu), int(m), check)
+    model = tuple(cov) if cov is not None else float(nu)
+    return VecchiaLogLik.apply(theta, locs, z, nbr, model, int(m), check)
 
 
 # ------------------------------------------------------------------ batched

@@ -247,3 +247,21 @@ def test_great_circle_grid_search_matches_oracle(v, region):
     rows = np.unique(np.concatenate([np.arange(8150, 8300), rng.choice(n, 1500, replace=False)]))
     np.testing.assert_array_equal(got.cpu().numpy()[rows], oracle.knn_rows(locs, m, rows=rows, metric=1, threads=16))
     np.testing.assert_array_equal(gq.cpu().numpy(), oracle.knn_query(locs, q, m, metric=1, threads=16))
+
+
+def test_autograd_under_a_covariance_model(v):
+    """loglik(..., cov=...) differentiates through the adjoint kernel for the real-data model."""
+    import torch
+    rng = np.random.default_rng(1550)
+    n, m = 900, 25
+    locs, z = field(rng, n, 1)
+    nbr = oracle.knn_rows(locs, m, metric=1, threads=16)
+    cov, theta = CASES[4]
+    dev = torch.device("cuda:0")
+    L, Z, N = (torch.from_numpy(a).to(dev) for a in (locs, z, nbr))
+    th = torch.tensor(theta, dtype=torch.float64, device=dev, requires_grad=True)
+    ell = v.loglik(L, Z, N, th, 0.0, m, cov=cov)
+    ell.backward()
+    want, gwant = oracle.loglik_cov(locs, z, nbr, m, cov, theta, with_grad=True, threads=16)
+    assert abs(ell.item() - want) <= REL_VALUE * abs(want)
+    np.testing.assert_allclose(th.grad.cpu().numpy(), gwant, rtol=REL_GRAD, atol=REL_GRAD * np.abs(gwant).max())
