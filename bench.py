@@ -211,6 +211,92 @@ def realdata_times(v, stream, reps: int = 2):
             "predict_frac": p_flops / (p_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "status_ok": ok}
 
 
+def multifield_times(v, stream, reps: int = 3):
+    """The 32-field workload (n log-uniform in [1e4, 5e5], m uniform in 10..150, Matern nu = 3/2, one
+    theta per field, value + gradient): 32 per-field calls with the built-in default variants against
+    one batched plan, with variants autotuned per m, replayed from a captured graph; then 1024 small
+    fields the same two ways, where per-call launch costs dominate.  Best of `reps` HIP-event timings."""
+    import torch
+
+    import workloads as wl
+
+    w = wl.config_multifield(knn_threads=min(os.cpu_count() or 1, 16))
+    dev = torch.device("cuda:0")
+    fields = [tuple(torch.from_numpy(a).to(dev) for a in (f.locs, f.z, f.nbr)) + (f.m,) for f in w.fields]
+    thetas = torch.from_numpy(np.stack([f.thetas[0] for f in w.fields])).to(dev).reshape(-1, 1, 3).contiguous()
+    nsum = sum(f.n for f in w.fields)
+    wss = [torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev) for f in w.fields]
+    outs = [(torch.empty(1, dtype=torch.float64, device=dev), torch.empty(3, dtype=torch.float64, device=dev),
+             torch.empty(1, dtype=torch.int64, device=dev)) for _ in w.fields]
+
+    def plain():
+        for q, (L, Z, N, m) in enumerate(fields):
+            o, g, st = outs[q]
+            v.vecchia_loglik_grad(L, Z, N, m, 1.5, thetas[q, 0], out=o, grad=g, status=st, ws=wss[q], stream=stream)
+
+    def best_ms(fn):
+        ts = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return min(ts[1:])
+
+    # plain: the built-in default variant of every m
+    saved = {f.m: v.vecchia_get_variant(f.m, True) for f in w.fields}
+    for mm in saved:
+        v.vecchia_set_variant(mm, True, "auto")
+    p_ms = best_ms(plain)
+    # batched: variants autotuned per m on each field's own points, then one plan and one graph
+    tuned = {}
+    for q, (L, Z, N, m) in enumerate(fields):
+        if m not in tuned:
+            tuned[m], _ = v.vecchia_autotune(L, Z, N, m, 1.5, thetas[q, 0].contiguous(), True,
+                                             sample=min(w.fields[q].n, 50000), reps=2)
+    plan = v.BatchedPlan(fields, 1, 1.5, True)
+    b_out, b_grad, b_st = plan.outputs()
+    graph = plan.capture(thetas, b_out, b_grad, b_st)
+    b_ms = best_ms(lambda: graph.launch(stream))
+    graph.close()
+    plan.close()
+    for mm, var in saved.items():
+        v.vecchia_set_variant(mm, True, var if mm == 120 else "auto")
+    changed = sum(1 for q, f in enumerate(w.fields) if tuned[f.m] != v.vecchia_get_variant(f.m, True))
+    # many small fields (1024 fields of 2,000 points, m = 30): per-call launch costs against one graph
+    rng = np.random.default_rng(2404)
+    small = []
+    for _ in range(1024):
+        locs = wl.uniform_locations(rng, 2000)
+        small.append(wl.Field(locs, rng.standard_normal(2000), wl.nearest_previous_neighbours(locs, 30), 30, 1.5,
+                              np.array([[1.0, 0.1, 1e-3]])))
+    sf = [tuple(torch.from_numpy(a).to(dev) for a in (f.locs, f.z, f.nbr)) + (f.m,) for f in small]
+    sth = torch.tensor([1.0, 0.1, 1e-3], dtype=torch.float64, device=dev)
+    sws = torch.empty(v.vecchia_workspace_size(2000, 30), dtype=torch.uint8, device=dev)
+    so, sg, sst = outs[0]
+
+    def plain_small():
+        for (L, Z, N, m) in sf:
+            v.vecchia_loglik_grad(L, Z, N, m, 1.5, sth, out=so, grad=sg, status=sst, ws=sws, stream=stream)
+
+    sp_ms = best_ms(plain_small)
+    splan = v.BatchedPlan(sf, 1, 1.5, True)
+    s_out, s_grad, s_st = splan.outputs()
+    sthetas = sth.reshape(1, 1, 3).expand(len(sf), 1, 3).contiguous()
+    sgraph = splan.capture(sthetas, s_out, s_grad, s_st)
+    sb_ms = best_ms(lambda: sgraph.launch(stream))
+    sgraph.close()
+    splan.close()
+    return {"workload": f"{len(fields)} fields, n log-uniform [1e4, 5e5] (sum {nsum}), m 10..150, nu=1.5, "
+                        "value+gradient", "plain_ms": p_ms, "batched_ms": b_ms,
+            "plain_cond_per_s": nsum / (p_ms * 1e-3), "batched_cond_per_s": nsum / (b_ms * 1e-3),
+            "batched_speedup": p_ms / b_ms, "fields_with_tuned_variant_other_than_default": changed,
+            "small_fields": {"workload": "1024 fields of 2,000 uniform points, m=30, nu=1.5, value+gradient",
+                             "plain_ms": sp_ms, "batched_ms": sb_ms, "batched_speedup": sp_ms / sb_ms}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +312,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-realdata", action="store_true",
                     help="skip the real-data configuration leg (power exponential, great-circle, kriging)")
+    ap.add_argument("--no-multifield", action="store_true",
+                    help="skip the 32-field leg (per-field calls against one batched launch)")
     ap.add_argument("--no-preprocess", action="store_true",
                     help="skip timing the GPU conditioning-set search and Morton ordering of the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -357,6 +445,8 @@ def main():
         rec["preprocess"] = preprocess_times(v, f, locs, stream)
     if not args.no_realdata:
         rec["realdata"] = realdata_times(v, stream)
+    if not args.no_multifield:
+        rec["multifield"] = multifield_times(v, stream)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(f, True)
     print(json.dumps(rec), flush=True)

@@ -199,12 +199,17 @@ inline bool variant_feasible(int variant, int m) {
     return tiles_per_wave(T, W) <= 20;
 }
 
-inline int default_variant(int m) {
+// Built-in choice when the variant table has no entry: the fastest variant
+// per tile count measured on MI355X (value and value + gradient, nu = 1/2,
+// 3/2, 5/2, 60,000 uniform points).  Three tile rows favour one wavefront
+// with the gradient and two without; up to six rows two wavefronts; beyond,
+// four (eight wavefronts lose to their barriers at every size).
+inline int default_variant(int m, bool grad) {
     const int T = tile_rows(m);
     if (T <= 2) return V_TILE_W1;
-    if (T <= 4) return V_TILE_W2;
-    if (T <= 8) return V_TILE_W4;
-    return V_TILE_W8;
+    if (T == 3) return grad ? V_TILE_W1 : V_TILE_W2;
+    if (T <= 6) return V_TILE_W2;
+    return V_TILE_W4;
 }
 
 template <int KC, bool GRAD, int T, int W>

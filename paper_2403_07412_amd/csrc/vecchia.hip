@@ -31,7 +31,7 @@ int g_variant[2][VECCHIA_MAX_M + 1] = {};
 
 int resolve_variant(int m, bool grad, int requested) {
     int v = requested != V_AUTO ? requested : g_variant[grad ? 1 : 0][m];
-    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m);
+    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m, grad);
     return v;
 }
 
