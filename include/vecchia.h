@@ -260,6 +260,10 @@ typedef struct vecchia_graph vecchia_graph;
 int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
                         vecchia_plan **plan);
 
+/* vecchia_plan_create under any covariance model (vecchia_cov; smoothness fixed). */
+int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov,
+                            int32_t with_grad, vecchia_plan **plan);
+
 /* Workspace (bytes) vecchia_loglik_batched needs: 36 bytes per (field, theta,
  * point) plus a little for partial sums; 0 for a NULL plan. */
 size_t vecchia_plan_workspace_size(const vecchia_plan *plan);

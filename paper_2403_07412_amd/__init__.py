@@ -102,6 +102,8 @@ def _load():
         PP = ctypes.POINTER(ctypes.c_void_p)
         lib.vecchia_plan_create.restype = ctypes.c_int
         lib.vecchia_plan_create.argtypes = [ctypes.POINTER(_Field), I32, I32, D, I32, PP]
+        lib.vecchia_plan_create_cov.restype = ctypes.c_int
+        lib.vecchia_plan_create_cov.argtypes = [ctypes.POINTER(_Field), I32, I32, ctypes.POINTER(Cov), I32, PP]
         lib.vecchia_plan_workspace_size.restype = SZ
         lib.vecchia_plan_workspace_size.argtypes = [P]
         lib.vecchia_plan_num_classes.restype = ctypes.c_int
@@ -469,14 +471,16 @@ def _field_struct(locs, z, nbr, m):
 
 class BatchedPlan:
     """vecchia_plan_* over a list of fields (each (locs, z, nbr, m) of device tensors), ntheta parameter
-    vectors per field.  Keeps references to the field tensors for the plan's lifetime."""
+    vectors per field, Matern nu on Euclidean distances or the covariance model cov = (family, metric,
+    smoothness) when given.  Keeps references to the field tensors for the plan's lifetime."""
 
-    def __init__(self, fields, ntheta: int, nu: float, with_grad: bool):
+    def __init__(self, fields, ntheta: int, nu: float, with_grad: bool, cov=None):
         self._fields = [tuple(f) for f in fields]
         arr = (_Field * len(self._fields))(*[_field_struct(*f) for f in self._fields])
         handle = ctypes.c_void_p()
-        _check(_load().vecchia_plan_create(arr, len(self._fields), int(ntheta), float(nu), int(bool(with_grad)),
-                                           ctypes.byref(handle)), "vecchia_plan_create")
+        c = _cov(cov if cov is not None else (MATERN, EUCLIDEAN, nu))
+        _check(_load().vecchia_plan_create_cov(arr, len(self._fields), int(ntheta), ctypes.byref(c),
+                                               int(bool(with_grad)), ctypes.byref(handle)), "vecchia_plan_create")
         self.handle = handle
         self.nf, self.ntheta, self.nu, self.with_grad = len(self._fields), int(ntheta), float(nu), bool(with_grad)
         self.device = self._fields[0][1].device

@@ -78,7 +78,8 @@ __global__ void __launch_bounds__(kFinalizeThreads) batched_finalize_kernel(cons
 
 struct vecchia_plan {
     int32_t nf = 0, ntheta = 0;
-    int nuc = 0;
+    int nuc = 0;         // covariance code (launch_any)
+    double alpha = 1.0;  // power-exponential exponent
     bool grad = false;
     std::vector<FieldDev> fields;
     std::vector<EvalDev> evals;
@@ -138,6 +139,7 @@ int run_batched(const vecchia_plan *p, const double *thetas, double *out, double
         a.k.g = vals + 1;
         a.k.g_stride = 4;
         a.k.flags = flags;
+        a.k.alpha = p->alpha;
         a.t_begin = 0;
         a.t_end = C.item0.back();
         a.m_max = C.m_max;
@@ -164,9 +166,17 @@ extern "C" {
 
 int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
                         vecchia_plan **plan) {
+    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
+    return vecchia_plan_create_cov(fields, nf, ntheta, &cov, with_grad, plan);
+}
+
+int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov,
+                            int32_t with_grad, vecchia_plan **plan) {
     if (!plan) return VECCHIA_EINVAL;
     *plan = nullptr;
-    if (!fields || nf < 1 || ntheta < 1 || nu_code(nu) < 0) return VECCHIA_EINVAL;
+    double alpha = 1.0;
+    const int kc = cov_code(cov, &alpha);
+    if (!fields || nf < 1 || ntheta < 1 || kc < 0) return VECCHIA_EINVAL;
     if (nf > VECCHIA_MAX_FIELDS) return VECCHIA_EUNSUPPORTED;
     for (int32_t f = 0; f < nf; ++f) {
         const vecchia_field &F = fields[f];
@@ -179,7 +189,8 @@ int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta,
     if (!p) return VECCHIA_EINVAL;
     p->nf = nf;
     p->ntheta = ntheta;
-    p->nuc = nu_code(nu);
+    p->nuc = kc;
+    p->alpha = alpha;
     p->grad = with_grad != 0;
     int64_t rows = 0, pblocks = 0;
     for (int32_t f = 0; f < nf; ++f) {

@@ -264,6 +264,7 @@ int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
 // -1 otherwise), the variant a launch uses for (m, gradient), the host-side
 // variant table, and the launcher for any covariance code (0..7).
 int nu_code(double nu);
+int cov_code(const vecchia_cov *cov, double *alpha);
 int resolve_variant(int m, bool grad, int requested);
 extern int g_variant[2][VECCHIA_MAX_M + 1];
 int launch_any(int kc, bool grad, int variant, const EvalArgs &a, hipStream_t s);

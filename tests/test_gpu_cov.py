@@ -265,3 +265,35 @@ def test_autograd_under_a_covariance_model(v):
     want, gwant = oracle.loglik_cov(locs, z, nbr, m, cov, theta, with_grad=True, threads=16)
     assert abs(ell.item() - want) <= REL_VALUE * abs(want)
     np.testing.assert_allclose(th.grad.cpu().numpy(), gwant, rtol=REL_GRAD, atol=REL_GRAD * np.abs(gwant).max())
+
+
+def test_batched_plan_under_a_covariance_model(v):
+    """Fields of uneven n and m with several parameter vectors, power exponential on great-circle
+    distances, in one plan and one captured graph: every evaluation bitwise equal to its single call."""
+    import torch
+    rng = np.random.default_rng(1560)
+    cov = (1, 1, 0.8)
+    dev = torch.device("cuda:0")
+    fields = []
+    for n, m in ((3000, 10), (5000, 45), (2000, 70)):
+        locs, z = field(rng, n, 1)
+        nbr = oracle.knn_rows(locs, m, metric=1, threads=16)
+        fields.append(tuple(torch.from_numpy(a).to(dev) for a in (locs, z, nbr)) + (m,))
+    thetas = torch.from_numpy(np.stack([np.column_stack([rng.uniform(0.5, 2, 4), rng.uniform(20, 80, 4),
+                                                         rng.uniform(1e-3, 1e-2, 4)]) for _ in fields])).to(dev)
+    thetas = thetas.contiguous()
+    plan = v.BatchedPlan(fields, 4, 0.0, True, cov=cov)
+    out, grad, st = plan(thetas)
+    g_out, g_grad, g_st = plan.outputs()
+    graph = plan.capture(thetas, g_out, g_grad, g_st)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all() and (g_st.cpu().numpy() == 0).all()
+    assert torch.equal(out, g_out) and torch.equal(grad, g_grad)
+    for q, (L, Z, N, m) in enumerate(fields):
+        for p in range(4):
+            o, g, s = v.vecchia_loglik_cov(L, Z, N, m, cov, thetas[q, p].contiguous(), with_grad=True)
+            torch.cuda.synchronize()
+            assert o.item() == out[q, p].item() and torch.equal(g, grad[q, p])
+    graph.close()
+    plan.close()
