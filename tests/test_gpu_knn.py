@@ -128,3 +128,22 @@ def test_maxmin_order(v, case):
         got = v.vecchia_maxmin_order(torch.from_numpy(locs).cuda(), seed=seed)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(got.cpu().numpy(), oracle.maxmin_order(locs, seed))
+
+
+def test_query_and_maxmin_edge_cases(v):
+    import torch
+    dev = torch.device("cuda:0")
+    q = torch.rand((5, 2), dtype=torch.float64, device=dev)
+    empty = torch.empty((0, 2), dtype=torch.float64, device=dev)
+    for metric in (0, 1):
+        out = v.vecchia_knn_query(empty, q, 7, metric=metric)
+        torch.cuda.synchronize()
+        assert out.shape == (5, 7) and (out.cpu().numpy() == -1).all()
+    assert v.vecchia_knn_query(q, empty, 7).shape == (0, 7)
+    # non-finite coordinates still give a permutation (they fall into cell 0)
+    rng = np.random.default_rng(1710)
+    locs = rng.uniform(size=(500, 2))
+    locs[[3, 77, 400]] = np.nan
+    got = v.vecchia_maxmin_order(torch.from_numpy(locs).cuda(), seed=5).cpu().numpy()
+    assert sorted(got) == list(range(500))
+    assert v.vecchia_maxmin_order(empty).shape == (0,)
