@@ -325,7 +325,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's conditionals are independent and a multi-GPU run "
-              "would shard them by cost and all-reduce four doubles; this build measures one GPU's share.",
+              "would shard them by cost and all-reduce four doubles; it measures one GPU's share.",
               file=sys.stderr)
         sys.exit(2)
 

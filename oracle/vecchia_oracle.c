@@ -665,7 +665,7 @@ int64_t oracle_predict(const double *ref, const double *zref, int64_t n_ref, con
 
 /*
  * Morton (Z-order) ordering of the points (the ordering option of Sec. IV-A),
- * as read for this build: each coordinate is mapped to a 16-bit cell index
+ * as read here: each coordinate is mapped to a 16-bit cell index
  * q = floor((x - min) / (max - min) * 65536) clamped to [0, 65535] over the
  * bounding box (a zero extent maps to 0), the code interleaves the bits with
  * x in the even and y in the odd positions, and perm lists the point indices
