@@ -46,10 +46,10 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # scale factors.  It describes the kernel sources it was measured on only, so
 # it is reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "9b04a2016e46a63ead8ae050718d42a767bcfce361c1e9979a6a3703d89b06a7",
+    "sources_sha256": "97060c2b375faa65dbf53ba93c5fef70984faec2300ff8591345c59b19ed50e5",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 8461162.5625, "fetch_factor": 524288.0 / 262161.875,
-    "write_kib_raw": 2613832.90625, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 8461392.375, "fetch_factor": 524288.0 / 262160.9375,
+    "write_kib_raw": 2616436.0625, "write_factor": 524288.0 / 524288.0,
 }
 
 
