@@ -54,14 +54,28 @@ __host__ __device__ constexpr int tile_extra_vgprs(int T, int W) {
     return ((T == 5 && W == 4) || (T == 7 && W == 8)) ? 64 : 0;
 }
 
+// One more workgroup per CU is worth a few spilled registers: the kernel is
+// bound by the latency of each conditional's dependency chain, and one more
+// resident workgroup hides more of it than the spill code costs, as long as
+// each wave keeps at least 102 VGPRs (5 wavefronts per SIMD).  Measured at
+// m = 120 (T = 8, W = 4, value + gradient): 40 VGPRs spilled for a fourth
+// workgroup, 8 % faster; W = 2 with 72 spilled for a fifth was 40 % slower,
+// and W = 8 at 6 wavefronts per SIMD (85 VGPRs) lost up to a third.
+constexpr int kTileSpillAllowance = 40;
+constexpr int kTileMaxRaisedWaves = 5;
+
 __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool gcd = false) {
-    const int lds = (2 * T * 256 + 272 + (gcd ? 9 : 8) * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds::BYTES
+    const int lds = ((T + (T > 1 ? 2 : 1)) * 256 + 272 + (gcd ? 9 : 8) * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds::BYTES
     const int blocks_lds = 163840 / lds;
     const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 96 + tile_extra_vgprs(T, W);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
     const int blocks_regs = (wps_regs * 4) / W;      // workgroups per CU the registers allow
     int blocks = blocks_lds < blocks_regs ? blocks_lds : blocks_regs;
     if (blocks < 1) blocks = 1;
+    if (blocks + 1 <= blocks_lds) {                  // one more, if LDS allows and the spill stays small
+        const int wps1 = ((blocks + 1) * W + 3) / 4;
+        if (wps1 <= kTileMaxRaisedWaves && need - 512 / wps1 <= kTileSpillAllowance) blocks += 1;
+    }
     int wps = (blocks * W + 3) / 4;
     if (wps < 1) wps = 1;
     if (wps > 8) wps = 8;
@@ -77,12 +91,21 @@ __host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
 
 // LDS layout of the tiled kernel, in doubles.  The great-circle codes add
 // cos(latitude) of every row at the end; the other offsets do not depend on it.
+//
+// One array of T tile slots serves both the panel and the stored inverses:
+// while column t is processed, slot R > t holds the panel tile X_R, and
+// slot t' <= t holds Linv_t' in N-layout (gradient only), written once the
+// last TRSM of column t' is done.  A slot never holds both at once.  The
+// factorisation publishes Linv_t for the TRSM in T-layout to CUR[t % 2]:
+// the buffer it overwrites served column t - 2, whose readers all passed a
+// workgroup barrier since.  A single tile column needs one such buffer.
 template <int T, bool GCD = false>
 struct TileLds {
     static constexpr int KP = 16 * T;
-    static constexpr int LINV = 0;                  // [T][64 lanes][4]   inverse diagonal tiles, T-layout
-    static constexpr int PANEL = LINV + T * 256;    // [T][64 lanes][4]   current panel X_R, slot R
-    static constexpr int DIAG = PANEL + T * 256;    // [16][17]           diagonal tile, row-major
+    static constexpr int NCUR = T > 1 ? 2 : 1;
+    static constexpr int CUR = 0;                   // [NCUR][64 lanes][4] Linv_t of the current column, T-layout
+    static constexpr int SLOT = CUR + NCUR * 256;   // [T][64 lanes][4]   panel X_R (slot R > t), Linv_t N-layout (slot t)
+    static constexpr int DIAG = SLOT + T * 256;     // [16][17]           diagonal tile, row-major
     static constexpr int XY = DIAG + 272;           // [KP][2]            coordinates
     static constexpr int ZV = XY + 2 * KP;          // [KP]               observations
     static constexpr int YP = ZV + KP;              // [KP]               factor row k+1
@@ -94,7 +117,7 @@ struct TileLds {
     static constexpr int CL = EXPT + 2 * kExpTableSize;  // [KP]         cos(latitude) (great-circle codes only)
     static constexpr int TOTAL = CL + (GCD ? KP : 0);
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
-    static_assert(TOTAL == 2 * T * 256 + 272 + (GCD ? 9 : 8) * KP + 80 + 2 * kExpTableSize,
+    static_assert(TOTAL == (T + NCUR) * 256 + 272 + (GCD ? 9 : 8) * KP + 80 + 2 * kExpTableSize,
                   "occupancy estimate out of date");
 };
 
@@ -250,22 +273,20 @@ __device__ __forceinline__ void store_diag(const dvec4 &v, double *smem) {
     for (int r = 0; r < 4; ++r) smem[TileLds<T>::DIAG + j * 17 + 4 * r + g] = v[r];
 }
 
-// Rewrites Linv_t in the LINV area from T-layout (lane (g, j), register r:
-// Linv[j][4r + g]) to N-layout (lane (g, n), register r: Linv[4r + g][n]),
-// by the wave that owns it.  The four reads of every lane complete before
-// any write is issued, so the rewrite in place is safe within the wave.
+// Copies Linv_t from CUR[t % 2] in T-layout (lane (g, j), register r:
+// Linv[j][4r + g]) to slot t in N-layout (lane (g, n), register r:
+// Linv[4r + g][n]), by the wave that owns it.
 template <int T>
 __device__ __forceinline__ void linv_to_nlayout(int t, double *smem) {
     const int l = threadIdx.x % kWave, g = l / 16, j = l % 16;
-    double *Lt = smem + TileLds<T>::LINV + t * 256;
-    const dvec4 v = *reinterpret_cast<const dvec4 *>(Lt + l * 4);
-    wave_lds_sync();
+    const dvec4 v = *reinterpret_cast<const dvec4 *>(smem + TileLds<T>::CUR + (t & 1) * 256 + l * 4);
+    double *Lt = smem + TileLds<T>::SLOT + t * 256;
 #pragma unroll
     for (int r = 0; r < 4; ++r) Lt[(16 * (j % 4) + 4 * r + g) * 4 + j / 4] = v[r];
 }
 
 // Factors diagonal tile t, which the calling wave has stored row-major in the
-// DIAG area of LDS; publishes Linv_t (T-layout, lane-major) and records L_kk
+// DIAG area of LDS; publishes Linv_t (T-layout, lane-major) to CUR[t % 2] and records L_kk
 // and the part of factor row k+1 that falls in this tile.  Every row is
 // factored: the padding rows have pivot 1 and the observation row's diagonal
 // is 2^600 (augment_value), so their pivots are positive and nothing past row
@@ -337,7 +358,7 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
         for (int c = 0; c < 16; ++c)
             if (c < jy) smem[Ls::YP + base + c] = R[c];
     }
-    double *Li = smem + Ls::LINV + t * 256 + l * 4;
+    double *Li = smem + Ls::CUR + (t & 1) * 256 + l * 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) Li[r] = Wr[r];
     __builtin_amdgcn_s_setprio(0);
@@ -462,7 +483,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // With the gradient the register copy is kept in N-layout (the same
         // product with the operands swapped), the form the back substitution
         // feeds to the matrix cores.
-        const double *Li = smem + Ls::LINV + t * 256 + l * 4;
+        const double *Li = smem + Ls::CUR + (t & 1) * 256 + l * 4;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) == t && SR(s) > t) {
@@ -474,14 +495,15 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
                     if constexpr (GRAD) accn = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], li[q], accn, 0, 0, 0);
                 }
-                *reinterpret_cast<dvec4 *>(smem + Ls::PANEL + SR(s) * 256 + l * 4) = acc;
+                *reinterpret_cast<dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + l * 4) = acc;
                 tile[s] = GRAD ? accn : acc;
             }
         }
         __syncthreads();
         // Linv_t has served its last TRSM: the back substitution wants it in
-        // N-layout, rewritten in place by its owner (all reads of the wave
-        // complete before its writes)
+        // N-layout, copied by its owner to slot t (its panel tile X_t was
+        // last read by the trailing update of column t - 1, before the
+        // barriers above)
         if constexpr (GRAD) {
             if (w == tile_index(T, t, t) % W) linv_to_nlayout<T>(t, smem);
         }
@@ -489,8 +511,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) > t) {
-                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::PANEL + SR(s) * 256 + l * 4);
-                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::PANEL + SC(s) * 256 + l * 4);
+                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + l * 4);
+                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * 256 + l * 4);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xc[q], xr[q], tile[s], 0, 0, 0);
@@ -551,7 +573,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const bool rhs_lane = j < 2;  // lanes of columns 0 and 1
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
-            const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::LINV + t * 256 + l * 4);
+            const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + t * 256 + l * 4);
             dvec4 xq;
 #pragma unroll
             for (int q = 0; q < 4; ++q) xq[q] = rhs_lane ? Q[2 * (16 * t + 4 * q + g) + j] : 0.0;

@@ -201,13 +201,15 @@ inline bool variant_feasible(int variant, int m) {
 
 // Built-in choice when the variant table has no entry: the fastest variant
 // per tile count measured on MI355X (value and value + gradient, nu = 1/2,
-// 3/2, 5/2, 60,000 uniform points).  Three tile rows favour one wavefront
-// with the gradient and two without; up to six rows two wavefronts; beyond,
-// four (eight wavefronts lose to their barriers at every size).
+// 3/2, 5/2, 60,000 uniform points; rows 4 with the gradient re-measured at
+// 300,000 points, nu = 1/2, once the occupancy targets allowed a fifth
+// wavefront per SIMD).  Three and four tile rows favour one wavefront with
+// the gradient and two without; up to six rows two wavefronts; beyond, four
+// (eight wavefronts lose to their barriers at every size).
 inline int default_variant(int m, bool grad) {
     const int T = tile_rows(m);
     if (T <= 2) return V_TILE_W1;
-    if (T == 3) return grad ? V_TILE_W1 : V_TILE_W2;
+    if (T <= 4) return grad ? V_TILE_W1 : V_TILE_W2;
     if (T <= 6) return V_TILE_W2;
     return V_TILE_W4;
 }
