@@ -476,6 +476,11 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     // blocked right-looking Cholesky
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
+        // the lane's offset inside a tile slot, opaque to the compiler in every
+        // step: otherwise it hoists one address register per slot out of the
+        // loop, which at this register budget spill to scratch
+        int lo = l * 4;
+        asm volatile("" : "+v"(lo));
         // 1. diagonal tile t: fully updated, and stored to DIAG by its owner
         if (w == tile_index(T, t, t) % W) factor_diag<T>(t, k, smem);
         __syncthreads();
@@ -483,7 +488,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // With the gradient the register copy is kept in N-layout (the same
         // product with the operands swapped), the form the back substitution
         // feeds to the matrix cores.
-        const double *Li = smem + Ls::CUR + (t & 1) * 256 + l * 4;
+        const double *Li = smem + Ls::CUR + (t & 1) * 256 + lo;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) == t && SR(s) > t) {
@@ -495,7 +500,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
                     if constexpr (GRAD) accn = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], li[q], accn, 0, 0, 0);
                 }
-                *reinterpret_cast<dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + l * 4) = acc;
+                *reinterpret_cast<dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + lo) = acc;
                 tile[s] = GRAD ? accn : acc;
             }
         }
@@ -511,8 +516,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) > t) {
-                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + l * 4);
-                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * 256 + l * 4);
+                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + lo);
+                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * 256 + lo);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xc[q], xr[q], tile[s], 0, 0, 0);
@@ -573,6 +578,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const bool rhs_lane = j < 2;  // lanes of columns 0 and 1
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
+            int qo = 2 * g + j;  // opaque per step, as in the factorisation loop
+            asm volatile("" : "+v"(qo));
             const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + t * 256 + l * 4);
             dvec4 xq;
 #pragma unroll
@@ -592,7 +599,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                     for (int q = 0; q < 4; ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], x[q], d, 0, 0, 0);
                     if (rhs_lane) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) Q[2 * (16 * SC(s) + 4 * r + g) + j] -= d[r];
+                        for (int r = 0; r < 4; ++r) Q[32 * SC(s) + 8 * r + qo] -= d[r];
                     }
                 }
             }
