@@ -46,10 +46,10 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # scale factors.  It describes the kernel sources it was measured on only, so
 # it is reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "97060c2b375faa65dbf53ba93c5fef70984faec2300ff8591345c59b19ed50e5",
+    "sources_sha256": "49ecc728110aa664f6ba8b9b093e12cf94c4b84d52df36ab14f0af3118f30a59",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 8461392.375, "fetch_factor": 524288.0 / 262160.9375,
-    "write_kib_raw": 2616436.0625, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 16933536.75, "fetch_factor": 524288.0 / 262161.6875,
+    "write_kib_raw": 27507389.3125, "write_factor": 524288.0 / 524288.0,
 }
 
 
