@@ -71,6 +71,10 @@ def _load():
         lib.oracle_knn_query.argtypes = [P, I64, P, I64, I32, I32, P, I32]
         lib.oracle_maxmin_order.restype = I64
         lib.oracle_maxmin_order.argtypes = [P, I64, ctypes.c_uint64, P]
+        lib.oracle_random_order.restype = I64
+        lib.oracle_random_order.argtypes = [I64, ctypes.c_uint64, P]
+        lib.oracle_mix64.restype = ctypes.c_uint64
+        lib.oracle_mix64.argtypes = [ctypes.c_uint64]
         lib.oracle_predict.restype = I64
         lib.oracle_predict.argtypes = [P, P, I64, P, I64, P, I32, I32, I32, D, P, P, P, I32]
         _lib = lib
@@ -293,6 +297,20 @@ def maxmin_order(locs, seed: int = 0):
     if rc != 0:
         raise OracleError(rc)
     return perm[:n]
+
+
+def random_order(n: int, seed: int = 0):
+    """Random ordering of n points: indices by ascending mix64(seed XOR i); returns the permutation."""
+    perm = np.empty(max(int(n), 1), dtype=np.int64)
+    rc = _load().oracle_random_order(int(n), ctypes.c_uint64(seed & (2 ** 64 - 1)), perm.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return perm[:n]
+
+
+def mix64(z: int) -> int:
+    """The splitmix64 finaliser of the ordering keys."""
+    return int(_load().oracle_mix64(ctypes.c_uint64(z & (2 ** 64 - 1))))
 
 
 def exact_loglik(locs, z, nu: float, theta) -> float:

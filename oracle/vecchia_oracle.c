@@ -892,3 +892,28 @@ int64_t oracle_exact_loglik(const double *locs, const double *z, int64_t n, doub
     free(logs);
     return rc;
 }
+
+/*
+ * Random ordering (Sec. IV-A orders the points at random before building the
+ * conditioning sets), as defined for this library: perm lists the point
+ * indices 0..n-1 by ascending key(i) = mix64(seed XOR i).  mix64 is a
+ * bijection on 64-bit words, so the keys are distinct and the order is a
+ * permutation.  Returns 0, ORACLE_EINVAL or ORACLE_ENOMEM.
+ */
+int64_t oracle_random_order(int64_t n, uint64_t seed, int64_t *perm) {
+    if (n < 0 || (n > 0 && !perm)) return ORACLE_EINVAL;
+    if (n == 0) return 0;
+    hkey_t *k = (hkey_t *)malloc(sizeof(hkey_t) * (size_t)n);
+    if (!k) return ORACLE_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        k[i].key = mix64(seed ^ (uint64_t)i);
+        k[i].idx = i;
+    }
+    qsort(k, (size_t)n, sizeof(hkey_t), hkey_cmp);
+    for (int64_t i = 0; i < n; ++i) perm[i] = k[i].idx;
+    free(k);
+    return 0;
+}
+
+/* The splitmix64 finaliser itself, for checking it against published outputs. */
+uint64_t oracle_mix64(uint64_t z) { return mix64(z); }
