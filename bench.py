@@ -11,9 +11,12 @@ Two forms are timed on the same inputs:
   plain    one vecchia_loglik_grad call per step with the built-in default
            kernel variant;
   batched  the variant chosen by the autotuner for (m, gradient), a batched
-           plan over the field, captured once into a HIP graph; one graph
-           launch per step.
-`value` is the batched form; the plain figures are reported beside it.
+           plan over the field (one persistent launch), captured once into a
+           HIP graph; one graph launch per step.
+`value` is the faster form; both are reported.  Further objects time the
+other workloads: the 250K jittered grid (forward), 64 parameter vectors at
+200K points (per-call against batched), the paper's m grid at 250K points,
+32 uneven fields, the real-data configuration and the preprocessing.
 
 Prints one JSON line.  Extra objects:
   roofline      algorithmic FP64 flops of the conditional kernel per launch
@@ -97,15 +100,39 @@ def workload_counts(n: int, m: int, with_grad: bool):
     return flops, evals, gather_bytes
 
 
-def cpu_baseline(field, with_grad: bool, target_s: float = 15.0):
-    """The oracle on a bounded random sample of the workload's conditionals (same inputs)."""
+def host_cpu_info():
+    """The host's processor model (lscpu), its logical CPU count, and the CPUs this process may use."""
+    import subprocess
+
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except Exception:
+        allowed = os.cpu_count() or 1
+    return {"lscpu_model": model, "nproc": os.cpu_count() or 1, "cpus_allowed": allowed}
+
+
+# The GPU box gives one GPU a share of 16 host CPUs, whatever nproc shows; the
+# oracle's OpenMP threads stay within that share.
+HOST_CPU_SHARE = 16
+
+
+def oracle_rate(field, with_grad: bool, threads: int, target_s: float, seed: int = 12345):
+    """Conditionals per second of the oracle on a random sample of the field's points grown until it takes
+    about target_s / 2 .. target_s seconds (the whole field if that is quicker)."""
     import oracle
 
-    threads = max(1, min(os.cpu_count() or 1, 16))
-    rng = np.random.default_rng(12345)
+    rng = np.random.default_rng(seed)
     th = field.thetas[0]
     size = 64
-    elapsed = 0.0
     while True:
         idx = np.sort(rng.choice(field.n, size, replace=False)).astype(np.int64)
         t0 = time.perf_counter()
@@ -113,11 +140,31 @@ def cpu_baseline(field, with_grad: bool, target_s: float = 15.0):
                      threads=threads)
         elapsed = time.perf_counter() - t0
         if elapsed >= target_s * 0.5 or size >= field.n:
-            break
+            return size, elapsed
         size = int(min(field.n, max(size * 2, size * target_s / max(elapsed, 1e-3) * 0.7)))
+
+
+def cpu_baseline(field, with_grad: bool, target_s: float = 15.0):
+    """The oracle on a bounded random sample of the workload's conditionals (same inputs), on every CPU of
+    the host share, plus single-thread rates of the two forward-only workloads (2,000 points, m = 30, in
+    full; the 250,000-point grid, m = 60, on a sample)."""
+    import workloads as wl
+
+    info = host_cpu_info()
+    threads = max(1, min(info["cpus_allowed"], HOST_CPU_SHARE))
+    size, elapsed = oracle_rate(field, with_grad, threads, target_s)
+    single = {}
+    small = wl.config_small().fields[0]
+    s_size, s_el = oracle_rate(small, False, 1, 2.0)
+    single["n2k_m30_nu0.5 value"] = {"conditionals_per_s": s_size / s_el, "sample": s_size, "seconds": s_el}
+    grid = wl.config_grid(knn_threads=threads).fields[0]
+    g_size, g_el = oracle_rate(grid, False, 1, 4.0)
+    single["n250k_m60_nu1.5_grid value"] = {"conditionals_per_s": g_size / g_el, "sample": g_size,
+                                            "seconds": g_el}
     return {"value": size / elapsed, "unit": "conditionals/s", "cores": threads, "kind": "oracle",
             "sample": f"{size} conditionals drawn uniformly from the {field.n}-point workload "
-                      f"({'value+gradient' if with_grad else 'value'}), {elapsed:.1f} s"}
+                      f"({'value+gradient' if with_grad else 'value'}), {elapsed:.1f} s",
+            "host": info, "single_thread": single}
 
 
 def preprocess_times(v, f, locs, stream, reps: int = 3):
@@ -209,6 +256,126 @@ def realdata_times(v, stream, reps: int = 2):
             "knn_query_ms": q_ms, "predict_ms": p_ms, "predict_per_s": nq / (p_ms * 1e-3),
             "predict_tflops": p_flops / (p_ms * 1e-3) / 1e12,
             "predict_frac": p_flops / (p_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "status_ok": ok}
+
+
+def event_ms(stream, fn, steps: int = 5, warmup: int = 2):
+    """Mean and minimum HIP-event time (ms) of fn() on `stream` over `steps` runs after `warmup`."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.mean(ts)), float(min(ts))
+
+
+def grid_forward_times(v, stream):
+    """The 250,000-point jittered grid, m = 60, Matern nu = 3/2, theta = (1, 0.05, 1e-6): one forward
+    (value-only) evaluation per call, the default variant."""
+    import torch
+
+    import workloads as wl
+
+    w = wl.config_grid(knn_threads=min(os.cpu_count() or 1, HOST_CPU_SHARE))
+    f = w.fields[0]
+    dev = torch.device("cuda:0")
+    L, Z, N = (torch.from_numpy(a).to(dev) for a in (f.locs, f.z, f.nbr))
+    th = torch.from_numpy(f.thetas[0].copy()).to(dev)
+    ws = torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int64, device=dev)
+    ms, ms_min = event_ms(stream, lambda: v.vecchia_loglik(L, Z, N, f.m, f.nu, th, out=out, status=st, ws=ws,
+                                                             stream=stream), steps=10)
+    if int(st.item()) != 0:
+        raise RuntimeError(f"grid workload: status {int(st.item())}")
+    flops, _, gbytes = workload_counts(f.n, f.m, False)
+    names = {val: k for k, val in v.VARIANTS.items()}
+    return {"workload": f"{w.name} value", "n": f.n, "m": f.m, "nu": f.nu, "ms": ms, "ms_min": ms_min,
+            "cond_per_s": f.n / (ms * 1e-3), "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,
+            "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "gather_gb_per_s": gbytes / (ms * 1e-3) / 1e9,
+            "variant": names.get(v.vecchia_get_variant(f.m, False)), "loglik": out.item()}
+
+
+def multitheta_times(v, stream):
+    """200,000 uniform points, m = 60, Matern nu = 5/2, 64 parameter vectors, value + gradient for each:
+    64 per-call evaluations against one batched plan over the 64 vectors replayed from a graph."""
+    import torch
+
+    import workloads as wl
+
+    w = wl.config_multitheta(knn_threads=min(os.cpu_count() or 1, HOST_CPU_SHARE))
+    f = w.fields[0]
+    P = f.thetas.shape[0]
+    dev = torch.device("cuda:0")
+    L, Z, N = (torch.from_numpy(a).to(dev) for a in (f.locs, f.z, f.nbr))
+    thetas = torch.from_numpy(f.thetas.reshape(1, P, 3).copy()).to(dev)
+    ws = torch.empty(v.vecchia_workspace_size(f.n, f.m), dtype=torch.uint8, device=dev)
+    outs = torch.empty((P, 1), dtype=torch.float64, device=dev)
+    grads = torch.empty((P, 3), dtype=torch.float64, device=dev)
+    sts = torch.empty((P, 1), dtype=torch.int64, device=dev)
+
+    def plain():
+        for q in range(P):
+            v.vecchia_loglik_grad(L, Z, N, f.m, f.nu, thetas[0, q], out=outs[q], grad=grads[q], status=sts[q],
+                                  ws=ws, stream=stream)
+
+    p_ms, p_min = event_ms(stream, plain, steps=3, warmup=1)
+    plan = v.BatchedPlan([(L, Z, N, f.m)], P, f.nu, True)
+    b_out, b_grad, b_st = plan.outputs()
+    graph = plan.capture(thetas, b_out, b_grad, b_st)
+    b_ms, b_min = event_ms(stream, lambda: graph.launch(stream), steps=3, warmup=1)
+    torch.cuda.synchronize()
+    ok = bool((sts == 0).all()) and bool((b_st == 0).all())
+    same = bool(torch.equal(b_out.reshape(-1), outs.reshape(-1))) and bool(torch.equal(b_grad.reshape(-1, 3), grads))
+    graph.close()
+    plan.close()
+    flops, _, _ = workload_counts(f.n, f.m, True)
+    conds = P * f.n
+    return {"workload": f"{w.name} value+gradient", "n": f.n, "m": f.m, "nu": f.nu, "thetas": P,
+            "plain_ms": p_ms, "batched_ms": b_ms, "plain_cond_per_s": conds / (p_ms * 1e-3),
+            "batched_cond_per_s": conds / (b_ms * 1e-3), "batched_speedup": p_ms / b_ms,
+            "batched_frac": P * flops / (b_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "plain_frac": P * flops / (p_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "status_ok": ok, "batched_equals_plain_bitwise": same}
+
+
+def m_sweep_times(v, stream, n: int = 250_000, ms=(10, 30, 60, 90, 120, 150), nu: float = 1.5):
+    """The paper's m grid (Sec. V-D, Fig. 7) at a fixed n: uniform points in random order, Matern nu = 3/2,
+    theta = (1, 0.1, 1e-4), value + gradient per call with the default variant; conditioning sets from the
+    GPU search."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(7001)
+    L = torch.from_numpy(rng.uniform(size=(n, 2))).to(dev)
+    Z = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    th = torch.tensor([1.0, 0.1, 1e-4], dtype=torch.float64, device=dev)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(3, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int64, device=dev)
+    names = {val: k for k, val in v.VARIANTS.items()}
+    rows = []
+    for m in ms:
+        N = v.vecchia_knn(L, int(m), stream=stream)
+        ws = torch.empty(v.vecchia_workspace_size(n, m), dtype=torch.uint8, device=dev)
+        t, t_min = event_ms(stream, lambda: v.vecchia_loglik_grad(L, Z, N, m, nu, th, out=out, grad=grad, status=st,
+                                                                   ws=ws, stream=stream))
+        if int(st.item()) != 0:
+            raise RuntimeError(f"m sweep m={m}: status {int(st.item())}")
+        flops, _, _ = workload_counts(n, m, True)
+        rows.append({"m": int(m), "ms": t, "cond_per_s": n / (t * 1e-3),
+                     "algorithmic_tflops": flops / (t * 1e-3) / 1e12,
+                     "frac": flops / (t * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "variant": names.get(v.vecchia_get_variant(int(m), True))})
+        del N, ws
+    return {"workload": f"n={n} uniform, Matern nu={nu}, value+gradient, m in {list(ms)}", "rows": rows}
 
 
 def multifield_times(v, stream, reps: int = 3):
@@ -314,6 +481,9 @@ def main():
                     help="skip the real-data configuration leg (power exponential, great-circle, kriging)")
     ap.add_argument("--no-multifield", action="store_true",
                     help="skip the 32-field leg (per-field calls against one batched launch)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads: the 250K grid forward pass, 64 parameter vectors at 200K "
+                         "points, and the m sweep")
     ap.add_argument("--no-preprocess", action="store_true",
                     help="skip timing the GPU conditioning-set search and Morton ordering of the workload")
     ap.add_argument("--copy-probe", action="store_true",
@@ -397,7 +567,8 @@ def main():
         print(f"# {form}: variant {var}; {args.steps} steps: wall {wall * 1e3 / args.steps:.3f} ms/step, events mean "
               f"{np.mean(launch_ms):.3f} ms (min {min(launch_ms):.3f}); loglik {ell:.12e} grad {g}",
               file=sys.stderr, flush=True)
-    main_form = "batched" if "batched" in results else "plain"
+    # the headline is the faster of the two forms; the other is reported beside it
+    main_form = min(results, key=lambda k: results[k][0])
     wall, launch_ms, _, _, variant = results[main_form]
     ms = float(np.mean(launch_ms))
 
@@ -426,10 +597,11 @@ def main():
                      "algorithmic_flops_per_launch": flops, "kernel_evals_per_launch": evals,
                      "gather_bytes_per_launch": gbytes, "launch_ms": ms},
     }
-    if "plain" in results and main_form != "plain":
-        pw, pl, _, _, pv = results["plain"]
-        rec["plain"] = {"value": f.n * args.steps / pw, "ms_per_step": pw * 1e3 / args.steps,
-                        "launch_ms": float(np.mean(pl)), "variant": names.get(pv, pv)}
+    for form, (fw, fl, _, _, fv) in results.items():
+        rec[form] = {"value": f.n * args.steps / fw, "ms_per_step": fw * 1e3 / args.steps,
+                     "launch_ms": float(np.mean(fl)), "variant": names.get(fv, fv)}
+    if len(results) == 2:
+        rec["batched_over_plain"] = rec["plain"]["ms_per_step"] / rec["batched"]["ms_per_step"]
     if args.traffic_kib is not None:
         rec["roofline"]["traffic"] = (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
     else:
@@ -441,6 +613,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if not args.no_configs:
+        rec["grid_forward"] = grid_forward_times(v, stream)
+        rec["multitheta"] = multitheta_times(v, stream)
+        rec["m_sweep"] = m_sweep_times(v, stream)
     if not args.no_preprocess:
         rec["preprocess"] = preprocess_times(v, f, locs, stream)
     if not args.no_realdata:

@@ -23,8 +23,9 @@
  *   - Array pointers marked [dev] are DEVICE pointers owned by the caller.  The
  *     library never frees them and keeps no reference after the call.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
- *     is asynchronous.  Entry points never synchronise the device, except the
- *     batched planner, which documents it.
+ *     is asynchronous.  The likelihood entry points never synchronise the
+ *     device and never allocate device memory; the autotuner, the orderings
+ *     and the estimation drivers document their synchronisation.
  *   - locs  [dev] double [n][2]  row-major coordinates, already in the ordering.
  *   - z     [dev] double [n]     observations (zero mean).
  *   - nbr   [dev] int32  [n][m]  row i lists its min(i, m) conditioning points,
@@ -247,15 +248,15 @@ typedef struct vecchia_graph vecchia_graph;
 
 /*
  * Plans the evaluation of nf fields (1..VECCHIA_MAX_FIELDS) under ntheta
- * parameter vectors each, at smoothness nu, with (with_grad != 0) or without
- * the gradient.  Evaluation e = f * ntheta + q is field f under theta q.
- * Fields are grouped by tile class ceil((m+2)/16); each class uses the kernel
- * variant that the variant table (vecchia_set_variant / vecchia_autotune) holds
- * for the largest m of the class.  The field arrays must stay valid while the
- * plan is used.  This call allocates a small device table (a few bytes per
- * field), creates one stream per extra class, and synchronises; it is not
- * meant for capture.  Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED
- * (m or nf too large) or VECCHIA_EHIP.
+ * parameter vectors each (nf * ntheta <= 2^31 - 1), at smoothness nu, with
+ * (with_grad != 0) or without the gradient.  Evaluation e = f * ntheta + q is
+ * field f under theta q.  Fields are grouped by tile class ceil((m+2)/16);
+ * each class uses the kernel variant that the variant table (vecchia_set_variant
+ * / vecchia_autotune) holds for the largest m of the class.  The plan is a host
+ * object: planning allocates no device memory, creates no stream and does not
+ * synchronise.  The field arrays must stay valid while the plan is used.
+ * Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED (m, nf or
+ * nf * ntheta too large).
  */
 int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
                         vecchia_plan **plan);
@@ -264,8 +265,9 @@ int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta,
 int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov,
                             int32_t with_grad, vecchia_plan **plan);
 
-/* Workspace (bytes) vecchia_loglik_batched needs: 36 bytes per (field, theta,
- * point) plus a little for partial sums; 0 for a NULL plan. */
+/* Workspace (bytes) vecchia_plan_loglik needs: the device table of the plan
+ * (64 bytes per field plus 12 per field and class), 36 bytes per (field,
+ * theta, point) and a little for partial sums; 0 for a NULL plan. */
 size_t vecchia_plan_workspace_size(const vecchia_plan *plan);
 
 /* Number of tile classes of the plan, and the tile rows, variant, field count
@@ -274,7 +276,7 @@ int vecchia_plan_num_classes(const vecchia_plan *plan);
 int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_rows, int32_t *variant,
                             int32_t *nfields, int64_t *items);
 
-/* Releases the plan, its device table and streams.  Not during its use. */
+/* Releases the plan (host memory).  Not while a graph captured from it is used. */
 int vecchia_plan_destroy(vecchia_plan *plan);
 
 /*
@@ -283,21 +285,34 @@ int vecchia_plan_destroy(vecchia_plan *plan);
  *   out    [dev] double [nf][ntheta]      log-likelihoods
  *   grad   [dev] double [nf][ntheta][3]   gradients (required iff the plan has them)
  *   status [dev] int64  [nf][ntheta]      per evaluation, as in the header notes
- *   ws     [dev] at least vecchia_plan_workspace_size(plan) bytes
- * The tile classes run concurrently on the plan's streams, forked from and
- * joined back into `stream` (which must not be the legacy null stream when
- * there is more than one class); all work is ordered after prior work on
- * `stream` and complete when later work on `stream` starts.  No allocation,
- * no synchronisation, no memset: capturable.  Each evaluation's sum uses the
- * same fixed order as vecchia_loglik, so with the same variant the results
- * are bitwise equal to single calls.  A plan must not be used by two host
- * threads at once.
+ *   ws     [dev] at least vecchia_plan_workspace_size(plan) bytes, 256-byte aligned
+ * Everything is enqueued on `stream`, in order: a few small launches write
+ * the plan's device table to the front of ws from their kernel arguments,
+ * then one launch per tile class evaluates its (field, theta, point) items
+ * (one workgroup per item, last points first), then the sums.  No allocation, no host copy, no synchronisation, no
+ * memset: capturable.  Each evaluation's sum uses the same fixed order as
+ * vecchia_loglik, so with the same variant the results are bitwise equal to
+ * single calls.  Calls that share a workspace must not overlap.
  */
-int vecchia_loglik_batched(const vecchia_plan *plan, const double *thetas, double *out, double *grad,
-                           int64_t *status, void *ws, size_t ws_bytes, void *stream);
+int vecchia_plan_loglik(const vecchia_plan *plan, const double *thetas, double *out, double *grad, int64_t *status,
+                        void *ws, size_t ws_bytes, void *stream);
 
 /*
- * Captures vecchia_loglik_batched with these arguments into a HIP graph on
+ * The one-call batched form (Matern, Euclidean): plans on the host and
+ * evaluates as vecchia_plan_loglik, with the same arguments and results.
+ *   fields  [host] vecchia_field[nf]
+ *   ws      [dev] at least vecchia_batched_workspace(fields, nf, ntheta) bytes
+ * The plan lives only during the call: everything the device needs travels
+ * in kernel arguments or is written into ws.  Returns as vecchia_plan_create
+ * and vecchia_plan_loglik.
+ */
+size_t vecchia_batched_workspace(const vecchia_field *fields, int32_t nf, int32_t ntheta);
+int vecchia_loglik_batched(const vecchia_field *fields, int32_t nf, const double *thetas, int32_t ntheta, double nu,
+                           int32_t with_grad, double *out, double *grad, int64_t *status, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/*
+ * Captures vecchia_plan_loglik with these arguments into a HIP graph on
  * `stream` (not the null stream) and instantiates it.  Replays read the device
  * arrays in place, so new parameter vectors are written into `thetas` between
  * launches.  vecchia_batched_graph_launch replays it on `stream`.
@@ -389,6 +404,18 @@ int vecchia_knn_query(const double *locs, int64_t n, const double *qlocs, int64_
  */
 size_t vecchia_morton_workspace_size(int64_t n);
 int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * vecchia_random_order: the random ordering of Sec. IV-A, reproducible from a
+ * seed: perm lists 0..n-1 by ascending key(i) = mix64(seed XOR i), mix64 the
+ * splitmix64 finaliser (a bijection on 64-bit words, so the keys are
+ * distinct).  Device radix sort, kernel launches only (capturable).
+ *   perm [dev] int64[n];  ws [dev] at least vecchia_random_order_workspace_size(n)
+ * Returns VECCHIA_OK, VECCHIA_EINVAL (n < 0, n > 2^31 - 1, null perm),
+ * VECCHIA_EWORKSPACE or VECCHIA_EHIP.
+ */
+size_t vecchia_random_order_workspace_size(int64_t n);
+int vecchia_random_order(int64_t n, uint64_t seed, int64_t *perm, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Approximate maxmin ordering: maxmin orders points so that each one is as

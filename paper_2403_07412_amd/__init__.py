@@ -27,7 +27,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvecchia.so")
+# the in-tree build; VECCHIA_LIB may name another build of the same sources
+LIB_PATH = os.environ.get("VECCHIA_LIB") or os.path.join(_HERE, "libvecchia.so")
 
 VECCHIA_MAX_M = 160
 VECCHIA_STATUS_THETA = -1
@@ -113,8 +114,12 @@ def _load():
                                                 ctypes.POINTER(I32), ctypes.POINTER(I64)]
         lib.vecchia_plan_destroy.restype = ctypes.c_int
         lib.vecchia_plan_destroy.argtypes = [P]
+        lib.vecchia_plan_loglik.restype = ctypes.c_int
+        lib.vecchia_plan_loglik.argtypes = [P, P, P, P, P, P, SZ, P]
+        lib.vecchia_batched_workspace.restype = SZ
+        lib.vecchia_batched_workspace.argtypes = [ctypes.POINTER(_Field), I32, I32]
         lib.vecchia_loglik_batched.restype = ctypes.c_int
-        lib.vecchia_loglik_batched.argtypes = [P, P, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_batched.argtypes = [ctypes.POINTER(_Field), I32, P, I32, D, I32, P, P, P, P, SZ, P]
         lib.vecchia_batched_graph_create.restype = ctypes.c_int
         lib.vecchia_batched_graph_create.argtypes = [P, P, P, P, P, P, SZ, P, PP]
         lib.vecchia_batched_graph_launch.restype = ctypes.c_int
@@ -128,6 +133,10 @@ def _load():
         lib.vecchia_knn_workspace_size.argtypes = [I64]
         lib.vecchia_knn.restype = ctypes.c_int
         lib.vecchia_knn.argtypes = [P, I64, I32, P, P, SZ, P]
+        lib.vecchia_random_order_workspace_size.restype = SZ
+        lib.vecchia_random_order_workspace_size.argtypes = [I64]
+        lib.vecchia_random_order.restype = ctypes.c_int
+        lib.vecchia_random_order.argtypes = [I64, ctypes.c_uint64, P, P, SZ, P]
         lib.vecchia_maxmin_workspace_size.restype = SZ
         lib.vecchia_maxmin_workspace_size.argtypes = [I64]
         lib.vecchia_maxmin_order.restype = ctypes.c_int
@@ -209,6 +218,39 @@ def _dev_check(*ts):
             raise ValueError("inputs must be contiguous device tensors")
 
 
+def _tensor_check(t, name: str, dtype, numel: int, device=None):
+    """Raises unless t is a contiguous device tensor of `dtype` with at least `numel` elements (on
+    `device` when given): the C ABI reads and writes that many elements through the raw pointer."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the inputs on {device}")
+    if t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements, has {t.numel()}")
+
+
+def _theta_check(theta, device, count: int = 1):
+    """theta: float64, exactly 3 * count elements, on the inputs' device."""
+    _tensor_check(theta, "theta", torch.float64, 3 * count, device)
+    if theta.numel() != 3 * count:
+        raise ValueError(f"theta must hold exactly {3 * count} float64 values, has {theta.numel()}")
+
+
+def _outputs_check(device, out=None, grad=None, status=None, n_out: int = 1):
+    if out is not None:
+        _tensor_check(out, "out", torch.float64, n_out, device)
+    if grad is not None:
+        _tensor_check(grad, "grad", torch.float64, 3 * n_out, device)
+    if status is not None:
+        _tensor_check(status, "status", torch.int64, n_out, device)
+
+
 def _stream(stream):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -227,6 +269,10 @@ def _as_inputs(locs, z, nbr, m):
     return n
 
 
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
+
+
 def _check(rc, what):
     if rc != 0:
         raise VecchiaError(rc, what)
@@ -238,7 +284,9 @@ def vecchia_workspace_size(n: int, m: int) -> int:
 
 def _workspace(n, m, device, ws):
     need = vecchia_workspace_size(n, m)
-    if ws is None or ws.numel() < need:
+    if ws is not None:
+        _dev_check(ws)
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(need, dtype=torch.uint8, device=device)
     return ws
 
@@ -249,10 +297,11 @@ def vecchia_loglik(locs, z, nbr, m: int, nu: float, theta, out=None, status=None
     dev = z.device
     out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
     status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
-    _dev_check(theta, out, status)
+    _theta_check(theta, dev)
+    _outputs_check(dev, out=out, status=status)
     ws = _workspace(n, m, dev, ws)
     rc = _load().vecchia_loglik(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu), _ptr(theta),
-                                _ptr(out), _ptr(status), _ptr(ws), ws.numel(), _stream(stream))
+                                _ptr(out), _ptr(status), _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_loglik")
     return out, status
 
@@ -265,10 +314,11 @@ def vecchia_loglik_grad(locs, z, nbr, m: int, nu: float, theta, out=None, grad=N
     out = torch.empty(1, dtype=torch.float64, device=dev) if out is None else out
     grad = torch.empty(3, dtype=torch.float64, device=dev) if grad is None else grad
     status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
-    _dev_check(theta, out, grad, status)
+    _theta_check(theta, dev)
+    _outputs_check(dev, out=out, grad=grad, status=status)
     ws = _workspace(n, m, dev, ws)
     rc = _load().vecchia_loglik_grad(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
-                                     _ptr(theta), _ptr(out), _ptr(grad), _ptr(status), _ptr(ws), ws.numel(),
+                                     _ptr(theta), _ptr(out), _ptr(grad), _ptr(status), _ptr(ws), _nbytes(ws),
                                      _stream(stream))
     _check(rc, "vecchia_loglik_grad")
     return out, grad, status
@@ -288,7 +338,7 @@ def vecchia_loglik_terms(locs, z, nbr, m: int, nu: float, theta, idx=None, with_
     terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
     gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
     status = torch.empty(1, dtype=torch.int64, device=dev)
-    _dev_check(theta)
+    _theta_check(theta, dev)
     rc = _load().vecchia_loglik_terms(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
                                       _ptr(theta), _ptr(idx), nidx, _ptr(terms), _ptr(gterms), _ptr(status),
                                       _stream(stream))
@@ -306,12 +356,13 @@ def vecchia_loglik_cov(locs, z, nbr, m: int, cov, theta, with_grad: bool = False
     if with_grad and grad is None:
         grad = torch.empty(3, dtype=torch.float64, device=dev)
     status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
-    _dev_check(theta, out, grad if with_grad else None, status)
+    _theta_check(theta, dev)
+    _outputs_check(dev, out=out, grad=grad if with_grad else None, status=status)
     ws = _workspace(n, m, dev, ws)
     c = _cov(cov)
     rc = _load().vecchia_loglik_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, ctypes.byref(c),
                                     _ptr(theta), _ptr(out), _ptr(grad) if with_grad else None, _ptr(status),
-                                    _ptr(ws), ws.numel(), _stream(stream))
+                                    _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_loglik_cov")
     return out, (grad if with_grad else None), status
 
@@ -330,7 +381,7 @@ def vecchia_loglik_terms_cov(locs, z, nbr, m: int, cov, theta, idx=None, with_gr
     terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
     gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
     status = torch.empty(1, dtype=torch.int64, device=dev)
-    _dev_check(theta)
+    _theta_check(theta, dev)
     c = _cov(cov)
     rc = _load().vecchia_loglik_terms_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, ctypes.byref(c),
                                           _ptr(theta), _ptr(idx), nidx, _ptr(terms), _ptr(gterms), _ptr(status),
@@ -356,7 +407,11 @@ def vecchia_predict(locs, z, qlocs, nbr, m: int, cov, theta, mean=None, var=None
     mean = torch.empty(max(nq, 1), dtype=torch.float64, device=dev) if mean is None else mean
     var = torch.empty(max(nq, 1), dtype=torch.float64, device=dev) if var is None else var
     status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
-    _dev_check(locs, z, qlocs, nbr if m > 0 else None, theta, mean, var, status)
+    _dev_check(locs, z, qlocs, nbr if m > 0 else None)
+    _theta_check(theta, dev)
+    _tensor_check(mean, "mean", torch.float64, nq, dev)
+    _tensor_check(var, "var", torch.float64, nq, dev)
+    _tensor_check(status, "status", torch.int64, 1, dev)
     c = _cov(cov)
     rc = _load().vecchia_predict(_ptr(locs), _ptr(z), n, _ptr(qlocs), nq, _ptr(nbr) if m > 0 else None, m,
                                  ctypes.byref(c), _ptr(theta), _ptr(mean), _ptr(var), _ptr(status), _stream(stream))
@@ -389,11 +444,12 @@ def vecchia_loglik_variant(locs, z, nbr, m: int, nu: float, theta, variant, with
     if with_grad and grad is None:
         grad = torch.empty(3, dtype=torch.float64, device=dev)
     status = torch.empty(1, dtype=torch.int64, device=dev) if status is None else status
-    _dev_check(theta, out, grad if with_grad else None, status)
+    _theta_check(theta, dev)
+    _outputs_check(dev, out=out, grad=grad if with_grad else None, status=status)
     ws = _workspace(n, m, dev, ws)
     rc = _load().vecchia_loglik_variant(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
                                         _ptr(theta), _variant_id(variant), _ptr(out),
-                                        _ptr(grad) if with_grad else None, _ptr(status), _ptr(ws), ws.numel(),
+                                        _ptr(grad) if with_grad else None, _ptr(status), _ptr(ws), _nbytes(ws),
                                         _stream(stream))
     _check(rc, "vecchia_loglik_variant")
     return out, (grad if with_grad else None), status
@@ -414,7 +470,7 @@ def vecchia_loglik_terms_variant(locs, z, nbr, m: int, nu: float, theta, variant
     terms = torch.empty(max(nidx, 1), dtype=torch.float64, device=dev)
     gterms = torch.empty((max(nidx, 1), 3), dtype=torch.float64, device=dev) if with_grad else None
     status = torch.empty(1, dtype=torch.int64, device=dev)
-    _dev_check(theta)
+    _theta_check(theta, dev)
     rc = _load().vecchia_loglik_terms_variant(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
                                               _ptr(theta), _variant_id(variant), _ptr(idx), nidx, _ptr(terms),
                                               _ptr(gterms), _ptr(status), _stream(stream))
@@ -436,7 +492,8 @@ class VecchiaLogLik(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, theta, locs, z, nbr, model, m, check):
-        theta_c = theta.detach().contiguous()
+        _theta_check(theta, z.device)
+        theta_c = theta.detach()
         cov = model if isinstance(model, (tuple, list, Cov)) else (MATERN, EUCLIDEAN, float(model))
         out, grad, status = vecchia_loglik_cov(locs, z, nbr, m, cov, theta_c, with_grad=ctx.needs_input_grad[0])
         if ctx.needs_input_grad[0]:
@@ -497,6 +554,13 @@ class BatchedPlan:
             out.append((T.value, var.value, nfc.value, items.value))
         return out
 
+    def _check_arrays(self, thetas, out, grad, status):
+        ne = self.nf * self.ntheta
+        _theta_check(thetas, self.device, ne)
+        _outputs_check(self.device, out=out, grad=grad, status=status, n_out=ne)
+        if self.with_grad and grad is None:
+            raise ValueError("the plan evaluates gradients: grad is required")
+
     def outputs(self):
         dev = self.device
         out = torch.empty((self.nf, self.ntheta), dtype=torch.float64, device=dev)
@@ -505,27 +569,27 @@ class BatchedPlan:
         return out, grad, status
 
     def __call__(self, thetas, out=None, grad=None, status=None, stream=None):
-        """vecchia_loglik_batched: thetas [nf][ntheta][3] float64 device tensor -> (out, grad|None, status)."""
+        """vecchia_plan_loglik: thetas [nf][ntheta][3] float64 device tensor -> (out, grad|None, status)."""
         if tuple(thetas.shape) != (self.nf, self.ntheta, 3) or thetas.dtype != torch.float64:
             raise ValueError("thetas must be float64 [nf][ntheta][3]")
         o, g, st = self.outputs()
         out = o if out is None else out
         grad = (g if grad is None else grad) if self.with_grad else None
         status = st if status is None else status
-        _dev_check(thetas, out, grad, status)
-        rc = _load().vecchia_loglik_batched(self.handle, _ptr(thetas), _ptr(out), _ptr(grad), _ptr(status),
-                                            _ptr(self.ws), self.ws.numel(), _stream(stream))
-        _check(rc, "vecchia_loglik_batched")
+        self._check_arrays(thetas, out, grad, status)
+        rc = _load().vecchia_plan_loglik(self.handle, _ptr(thetas), _ptr(out), _ptr(grad), _ptr(status),
+                                            _ptr(self.ws), _nbytes(self.ws), _stream(stream))
+        _check(rc, "vecchia_plan_loglik")
         return out, grad, status
 
     def capture(self, thetas, out, grad, status, stream=None):
         """vecchia_batched_graph_create on a side stream; returns a BatchedGraph bound to these arrays."""
-        _dev_check(thetas, out, grad, status)
+        self._check_arrays(thetas, out, grad, status)
         s = stream if stream is not None else torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         handle = ctypes.c_void_p()
         rc = _load().vecchia_batched_graph_create(self.handle, _ptr(thetas), _ptr(out), _ptr(grad), _ptr(status),
-                                                  _ptr(self.ws), self.ws.numel(), ctypes.c_void_p(s.cuda_stream),
+                                                  _ptr(self.ws), _nbytes(self.ws), ctypes.c_void_p(s.cuda_stream),
                                                   ctypes.byref(handle))
         _check(rc, "vecchia_batched_graph_create")
         return BatchedGraph(handle, self, (thetas, out, grad, status))
@@ -540,6 +604,45 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+def vecchia_batched_workspace(fields, ntheta: int) -> int:
+    """Workspace bytes of vecchia_loglik_batched for these fields (each (locs, z, nbr, m))."""
+    fs = [tuple(f) for f in fields]
+    arr = (_Field * len(fs))(*[_field_struct(*f) for f in fs])
+    return int(_load().vecchia_batched_workspace(arr, len(fs), int(ntheta)))
+
+
+def vecchia_loglik_batched(fields, thetas, nu: float, with_grad: bool, out=None, grad=None, status=None, ws=None,
+                           stream=None):
+    """The one-call batched form: fields = [(locs, z, nbr, m)], thetas float64 [nf][ntheta][3] on the
+    device; returns (out [nf][ntheta], grad [nf][ntheta][3] | None, status [nf][ntheta])."""
+    fs = [tuple(f) for f in fields]
+    nf = len(fs)
+    if nf < 1:
+        raise ValueError("at least one field")
+    if thetas.dim() != 3 or thetas.shape[0] != nf or thetas.shape[2] != 3:
+        raise ValueError("thetas must be float64 [nf][ntheta][3]")
+    ntheta = int(thetas.shape[1])
+    dev = fs[0][1].device
+    arr = (_Field * nf)(*[_field_struct(*f) for f in fs])
+    _theta_check(thetas, dev, nf * ntheta)
+    out = torch.empty((nf, ntheta), dtype=torch.float64, device=dev) if out is None else out
+    if with_grad and grad is None:
+        grad = torch.empty((nf, ntheta, 3), dtype=torch.float64, device=dev)
+    status = torch.empty((nf, ntheta), dtype=torch.int64, device=dev) if status is None else status
+    _outputs_check(dev, out=out, grad=grad if with_grad else None, status=status, n_out=nf * ntheta)
+    need = int(_load().vecchia_batched_workspace(arr, nf, ntheta))
+    if need == 0:
+        raise ValueError("vecchia_batched_workspace rejected the fields")
+    if ws is None or _nbytes(ws) < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    _dev_check(ws)
+    rc = _load().vecchia_loglik_batched(arr, nf, _ptr(thetas), ntheta, float(nu), int(bool(with_grad)), _ptr(out),
+                                        _ptr(grad) if with_grad else None, _ptr(status), _ptr(ws), _nbytes(ws),
+                                        _stream(stream))
+    _check(rc, "vecchia_loglik_batched")
+    return out, (grad if with_grad else None), status
 
 
 class BatchedGraph:
@@ -571,9 +674,9 @@ def vecchia_autotune(locs, z, nbr, m: int, nu: float, theta, with_grad: bool, sa
     ws = torch.empty(max(1, 40 * f.n), dtype=torch.uint8, device=z.device)
     best = ctypes.c_int32()
     us = (ctypes.c_double * 6)()
-    _dev_check(theta)
+    _theta_check(theta, z.device)
     rc = _load().vecchia_autotune(ctypes.byref(f), float(nu), int(bool(with_grad)), _ptr(theta), int(sample),
-                                  int(reps), _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(best), us)
+                                  int(reps), _ptr(ws), _nbytes(ws), _stream(stream), ctypes.byref(best), us)
     _check(rc, "vecchia_autotune")
     names = {v: k for k, v in VARIANTS.items()}
     return best.value, {names[v]: us[v] for v in range(1, 6) if us[v] >= 0}
@@ -625,9 +728,9 @@ def vecchia_knn(locs, m: int, out=None, ws=None, stream=None, metric: int = EUCL
         raise ValueError("out must be int32 [n][m]")
     _dev_check(out)
     need = vecchia_knn_workspace_size(n)
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
-    rc = _load().vecchia_knn_metric(_ptr(locs), n, int(m), int(metric), _ptr(out), _ptr(ws), ws.numel(),
+    rc = _load().vecchia_knn_metric(_ptr(locs), n, int(m), int(metric), _ptr(out), _ptr(ws), _nbytes(ws),
                                     _stream(stream))
     _check(rc, "vecchia_knn")
     return out
@@ -647,11 +750,30 @@ def vecchia_knn_query(locs, qlocs, m: int, metric: int = EUCLIDEAN, out=None, ws
         raise ValueError("out must be int32 [nq][m]")
     _dev_check(out)
     need = vecchia_knn_workspace_size(n)
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=qlocs.device)
     rc = _load().vecchia_knn_query(_ptr(locs), n, _ptr(qlocs), nq, int(m), int(metric), _ptr(out), _ptr(ws),
-                                   ws.numel(), _stream(stream))
+                                   _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_knn_query")
+    return out
+
+
+def vecchia_random_order(n: int, seed: int = 0, device=None, out=None, ws=None, stream=None):
+    """Random permutation of n points (int64 [n] on the device): indices by ascending splitmix64
+    finaliser of seed XOR i."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    n = int(n)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=dev)
+    if tuple(out.shape) != (n,) or out.dtype != torch.int64:
+        raise ValueError("out must be int64 [n]")
+    _dev_check(out)
+    need = int(_load().vecchia_random_order_workspace_size(n))
+    if ws is None or _nbytes(ws) < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=out.device)
+    rc = _load().vecchia_random_order(n, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(out), _ptr(ws),
+                                      _nbytes(ws), _stream(stream))
+    _check(rc, "vecchia_random_order")
     return out
 
 
@@ -668,10 +790,10 @@ def vecchia_maxmin_order(locs, seed: int = 0, out=None, ws=None, stream=None):
         raise ValueError("out must be int64 [n]")
     _dev_check(out)
     need = int(_load().vecchia_maxmin_workspace_size(n))
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
     rc = _load().vecchia_maxmin_order(_ptr(locs), n, ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(out),
-                                      _ptr(ws), ws.numel(), _stream(stream))
+                                      _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_maxmin_order")
     return out
 
@@ -688,9 +810,9 @@ def vecchia_morton_order(locs, out=None, ws=None, stream=None):
         raise ValueError("out must be int64 [n]")
     _dev_check(out)
     need = int(_load().vecchia_morton_workspace_size(n))
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=locs.device)
-    rc = _load().vecchia_morton_order(_ptr(locs), n, _ptr(out), _ptr(ws), ws.numel(), _stream(stream))
+    rc = _load().vecchia_morton_order(_ptr(locs), n, _ptr(out), _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_morton_order")
     return out
 
@@ -710,7 +832,7 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
     n = _as_inputs(locs, z, nbr, m)
     c = _cov(cov if cov is not None else (MATERN, EUCLIDEAN, nu))
     need = int(_load().vecchia_mle_workspace_size(n, m))
-    if ws is None or ws.numel() < need:
+    if ws is None or _nbytes(ws) < need:
         ws = torch.empty(need, dtype=torch.uint8, device=locs.device)
     th0 = (ctypes.c_double * 3)(*[float(x) for x in theta0])
     th = (ctypes.c_double * 3)()
@@ -720,7 +842,7 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
     ev = ctypes.c_int32()
     rc = _load().vecchia_mle_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, int(m), ctypes.byref(c),
                                  th0, ctypes.byref(options) if options is not None else None, th, ctypes.byref(ll),
-                                 gr, ctypes.byref(it), ctypes.byref(ev), _ptr(ws), ws.numel(), _stream(stream))
+                                 gr, ctypes.byref(it), ctypes.byref(ev), _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_mle")
     return {"theta": np.array(th[:]), "loglik": ll.value, "grad": np.array(gr[:]), "iterations": it.value,
             "evaluations": ev.value}
@@ -731,13 +853,16 @@ def vecchia_exact_loglik(locs, z, nu: float, theta, stream=None):
     """Exact log-likelihood (dense Cholesky on the GPU); z=None means y = 0.  Returns (out, status)."""
     if locs.dtype != torch.float64 or locs.dim() != 2 or locs.shape[1] != 2:
         raise ValueError("locs must be float64 [n][2]")
-    _dev_check(locs, z, theta)
+    _dev_check(locs, z)
+    _theta_check(theta, locs.device)
     n = locs.shape[0]
+    if z is not None and (z.dtype != torch.float64 or tuple(z.shape) != (n,)):
+        raise ValueError("z must be float64 [n]")
     ws = torch.empty(int(_load().vecchia_exact_workspace_size(n)), dtype=torch.uint8, device=locs.device)
     out = torch.empty(1, dtype=torch.float64, device=locs.device)
     status = torch.empty(1, dtype=torch.int64, device=locs.device)
     rc = _load().vecchia_exact_loglik(_ptr(locs), _ptr(z), n, float(nu), _ptr(theta), _ptr(out), _ptr(status),
-                                      _ptr(ws), ws.numel(), _stream(stream))
+                                      _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_exact_loglik")
     return out, status
 
@@ -762,7 +887,7 @@ def vecchia_dense_logdet(A, z=None, stream=None):
     quad = torch.empty(1, dtype=torch.float64, device=A.device) if z is not None else None
     status = torch.empty(1, dtype=torch.int64, device=A.device)
     rc = _load().vecchia_dense_logdet(_ptr(A), n, A.stride(0), _ptr(z), _ptr(logdet), _ptr(quad), _ptr(status),
-                                      _ptr(ws), ws.numel(), _stream(stream))
+                                      _ptr(ws), _nbytes(ws), _stream(stream))
     _check(rc, "vecchia_dense_logdet")
     return logdet, quad, status
 
@@ -770,15 +895,14 @@ def vecchia_dense_logdet(A, z=None, stream=None):
 def kl_curve(locs, ms, nu: float, theta, ordering: str = "random", seed: int = 0, stream=None) -> dict:
     """KL divergence of Eq. (9) against the conditioning size, for one ordering of the points.
 
-    ordering: "random" (a seeded permutation), "morton" (vecchia_morton_order),
+    ordering: "random" (vecchia_random_order), "morton" (vecchia_morton_order),
     "maxmin" (vecchia_maxmin_order) or "given" (as passed).  The exact log-likelihood is computed once; each m
     takes GPU conditioning sets and one Vecchia evaluation at y = 0.
     Returns {"ordering", "exact", "exact_seconds", "kl": {m: KL}}.
     """
     n = locs.shape[0]
     if ordering == "random":
-        g = torch.Generator().manual_seed(seed)
-        locs = locs[torch.randperm(n, generator=g).to(locs.device)].contiguous()
+        locs = locs[vecchia_random_order(n, seed=seed, device=locs.device, stream=stream)].contiguous()
     elif ordering == "morton":
         locs = locs[vecchia_morton_order(locs, stream=stream)].contiguous()
     elif ordering == "maxmin":

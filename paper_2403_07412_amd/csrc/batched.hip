@@ -2,13 +2,20 @@
 // m in one enqueue (or one graph launch), and the autotuner that picks the
 // kernel variant per conditioning-set size.
 //
-// A plan groups the fields by tile class T = ceil((m+2)/16).  Items of a class
-// are (field, theta, point) triples; one launch per class evaluates all of
-// them with the class's variant.  The classes run concurrently on plan-owned
-// streams forked from and joined back into the caller's stream.  A segmented
-// reduction then forms every evaluation (field, theta) with the same
-// fixed-order sum as the single-evaluation entry points, so a batched result
-// is bitwise equal to the single call with the same variant.
+// A plan (host memory only) groups the fields by tile class
+// T = ceil((m+2)/16).  Items of a class are (field, theta, point) triples;
+// one launch per class evaluates all of them with the class's variant, one
+// workgroup per item, last points first (their conditioning sets are the
+// full ones), so the short sets of the first points fill the tail.  The
+// classes run one after the other on the caller's stream.  A segmented reduction then forms every evaluation (field, theta)
+// with the same fixed-order sum as the single-evaluation entry points, so a
+// batched result is bitwise equal to the single call with the same variant.
+//
+// The device table the kernels read (fields, per-class field lists and item
+// offsets) lives at the front of the caller's workspace.  Each call writes it
+// there with small kernels that carry the bytes in their arguments, so the
+// library allocates no device memory, creates no streams and issues no host
+// copies: a call is only kernel launches, which graph capture records.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,52 +32,67 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// One evaluation: its rows of the per-point arrays and its reduce blocks.
-struct EvalDev {
-    int64_t vals0;  // first row
-    int64_t n;      // rows (points of the field)
-    int64_t pb0;    // first reduce block
-    int64_t nb;     // reduce blocks
+constexpr int kPutWords = 256;  // 8-byte words of table one writing launch carries (2 KB of kernel arguments)
+
+struct PutChunk {
+    uint64_t word0;  // first destination word
+    uint32_t nwords;
+    uint32_t pad;
+    uint64_t w[kPutWords];
 };
+
+// Copies a chunk of the host-built table from the kernel arguments to the workspace.
+__global__ void __launch_bounds__(kPutWords) put_words_kernel(uint64_t *__restrict__ dst, const PutChunk c) {
+    const uint32_t t = threadIdx.x;
+    if (t < c.nwords) dst[c.word0 + t] = c.w[t];
+}
 
 struct ClassPlan {
     int T = 0;
     int variant = 0;
     int32_t m_max = 0;
-    std::vector<int32_t> fidx;   // fields of the class
+    std::vector<int32_t> fidx;   // fields of the class, larger m first
     std::vector<int64_t> item0;  // prefix sums of ntheta * n over fidx (size nfc + 1)
     size_t off_fidx = 0, off_item0 = 0;
 };
 
-__global__ void __launch_bounds__(kReduceThreads) batched_reduce_kernel(const double *__restrict__ vals,
-                                                                        const int32_t *__restrict__ flags,
-                                                                        const EvalDev *__restrict__ evals,
-                                                                        int32_t nevals,
-                                                                        double *__restrict__ partial,
-                                                                        int64_t *__restrict__ pfail) {
-    const int64_t b = blockIdx.x;
-    int lo = 0, hi = nevals;
-    while (hi - lo > 1) {  // last evaluation whose first block is <= b
+// Last field whose first reduce block is <= b: the field owning block b
+// (fields without points own no block and share their successor's pb0).
+__device__ __forceinline__ int field_of_block(const FieldDev *__restrict__ fields, int nf, int64_t b) {
+    int lo = 0, hi = nf;
+    while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (evals[mid].pb0 <= b) lo = mid;
+        if (fields[mid].pb0 <= b) lo = mid;
         else hi = mid;
     }
-    // evaluations with n = 0 own no block; skip to the one that owns b
-    while (lo + 1 < nevals && evals[lo].nb == 0) ++lo;
-    const EvalDev E = evals[lo];
-    reduce_segment_block(vals + 4 * E.vals0, flags + E.vals0, E.n, b - E.pb0, partial + 8 * b, pfail + b);
+    return lo;
+}
+
+__global__ void __launch_bounds__(kReduceThreads) batched_reduce_kernel(const double *__restrict__ vals,
+                                                                        const int32_t *__restrict__ flags,
+                                                                        const FieldDev *__restrict__ fields,
+                                                                        int32_t nf, double *__restrict__ partial,
+                                                                        int64_t *__restrict__ pfail) {
+    const int64_t b = blockIdx.x;
+    const FieldDev F = fields[field_of_block(fields, nf, b)];
+    const int64_t q = (b - F.pb0) / F.nb;
+    const int64_t v0 = F.vals0 + q * F.n;
+    reduce_segment_block(vals + 4 * v0, flags + v0, F.n, b - F.pb0 - q * F.nb, partial + 8 * b, pfail + b);
 }
 
 __global__ void __launch_bounds__(kFinalizeThreads) batched_finalize_kernel(const double *__restrict__ partial,
                                                                             const int64_t *__restrict__ pfail,
-                                                                            const EvalDev *__restrict__ evals,
+                                                                            const FieldDev *__restrict__ fields,
+                                                                            int32_t ntheta,
                                                                             const double *__restrict__ thetas,
                                                                             double *__restrict__ out,
                                                                             double *__restrict__ grad,
                                                                             int64_t *__restrict__ status) {
     const int64_t e = blockIdx.x;
-    const EvalDev E = evals[e];
-    finalize_segment(partial + 8 * E.pb0, pfail + E.pb0, E.nb, thetas + 3 * e, out + e, grad ? grad + 3 * e : nullptr,
+    const FieldDev F = fields[e / ntheta];
+    const int64_t q = e % ntheta;
+    const int64_t p0 = F.pb0 + q * F.nb;
+    finalize_segment(partial + 8 * p0, pfail + p0, F.nb, thetas + 3 * e, out + e, grad ? grad + 3 * e : nullptr,
                      status + e);
 }
 
@@ -82,13 +104,9 @@ struct vecchia_plan {
     double alpha = 1.0;  // power-exponential exponent
     bool grad = false;
     std::vector<FieldDev> fields;
-    std::vector<EvalDev> evals;
     std::vector<ClassPlan> classes;
     int64_t total_rows = 0, total_pblocks = 0;
-    char *d_buf = nullptr;  // device copy of fields, evals and the class tables
-    size_t off_fields = 0, off_evals = 0;
-    std::vector<hipStream_t> streams;  // one per class after the first
-    std::vector<hipEvent_t> events;    // fork event + one join event per extra class
+    std::vector<uint64_t> table;  // host image of the device table (fields, class lists), 8-byte words
     size_t ws_vals = 0, ws_flags = 0, ws_partial = 0, ws_pfail = 0, ws_bytes = 0;
 };
 
@@ -99,41 +117,39 @@ struct vecchia_graph {
 
 namespace {
 
-void plan_release(vecchia_plan *p) {
-    if (!p) return;
-    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-    for (hipStream_t s : p->streams) (void)hipStreamDestroy(s);
-    if (p->d_buf) (void)hipFree(p->d_buf);
-    delete p;
-}
-
 int run_batched(const vecchia_plan *p, const double *thetas, double *out, double *grad, int64_t *status, void *ws,
                 size_t ws_bytes, hipStream_t s) {
     if (!p || !thetas || !out || !status || (p->grad && !grad)) return VECCHIA_EINVAL;
     if (!ws || ws_bytes < p->ws_bytes) return VECCHIA_EWORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return VECCHIA_EINVAL;
     char *w = (char *)ws;
+    uint64_t *table = (uint64_t *)w;
     double *vals = (double *)(w + p->ws_vals);
     int32_t *flags = (int32_t *)(w + p->ws_flags);
     double *partial = (double *)(w + p->ws_partial);
     int64_t *pfail = (int64_t *)(w + p->ws_pfail);
-    const FieldDev *dfields = (const FieldDev *)(p->d_buf + p->off_fields);
-    const EvalDev *devals = (const EvalDev *)(p->d_buf + p->off_evals);
+    const FieldDev *dfields = (const FieldDev *)w;  // the field array opens the table
 
-    const size_t nc = p->classes.size();
-    if (nc > 1) {
-        if (hipEventRecord(p->events[0], s) != hipSuccess) return VECCHIA_EHIP;
-        for (size_t c = 1; c < nc; ++c)
-            if (hipStreamWaitEvent(p->streams[c - 1], p->events[0], 0) != hipSuccess) return VECCHIA_EHIP;
+    // 1. the device table, from the kernel arguments of a few small launches
+    for (size_t w0 = 0; w0 < p->table.size(); w0 += kPutWords) {
+        PutChunk c;
+        c.word0 = w0;
+        c.nwords = (uint32_t)std::min<size_t>(kPutWords, p->table.size() - w0);
+        c.pad = 0;
+        std::copy(p->table.begin() + w0, p->table.begin() + w0 + c.nwords, c.w);
+        hipLaunchKernelGGL(put_words_kernel, dim3(1), dim3(kPutWords), 0, s, table, c);
     }
-    for (size_t c = 0; c < nc; ++c) {
+    const int nc = (int)p->classes.size();
+    // 2. one launch per tile class
+    for (int c = 0; c < nc; ++c) {
         const ClassPlan &C = p->classes[c];
-        hipStream_t cs = (c == 0) ? s : p->streams[c - 1];
         EvalArgs a{};
         a.k.theta = thetas;
         a.k.fields = dfields;
-        a.k.fidx = (const int32_t *)(p->d_buf + C.off_fidx);
-        a.k.item0 = (const int64_t *)(p->d_buf + C.off_item0);
+        a.k.fidx = (const int32_t *)(w + C.off_fidx);
+        a.k.item0 = (const int64_t *)(w + C.off_item0);
         a.k.nfc = (int32_t)C.fidx.size();
+        a.k.ntheta = p->ntheta;
         a.k.ell = vals;
         a.k.ell_stride = 4;
         a.k.g = vals + 1;
@@ -143,47 +159,43 @@ int run_batched(const vecchia_plan *p, const double *thetas, double *out, double
         a.t_begin = 0;
         a.t_end = C.item0.back();
         a.m_max = C.m_max;
-        const int rc = launch_any(p->nuc, p->grad, C.variant, a, cs);
+        const int rc = launch_any(p->nuc, p->grad, C.variant, a, s);
         if (rc != VECCHIA_OK) return rc;
     }
-    if (nc > 1) {
-        for (size_t c = 1; c < nc; ++c) {
-            if (hipEventRecord(p->events[c], p->streams[c - 1]) != hipSuccess) return VECCHIA_EHIP;
-            if (hipStreamWaitEvent(s, p->events[c], 0) != hipSuccess) return VECCHIA_EHIP;
-        }
-    }
+    // 3. fixed-order sums per evaluation
     if (p->total_pblocks > 0)
         hipLaunchKernelGGL(batched_reduce_kernel, dim3((unsigned)p->total_pblocks), dim3(kReduceThreads), 0, s, vals,
-                           flags, devals, (int32_t)p->evals.size(), partial, pfail);
-    hipLaunchKernelGGL(batched_finalize_kernel, dim3((unsigned)p->evals.size()), dim3(kFinalizeThreads), 0, s,
-                       partial, pfail, devals, thetas, out, p->grad ? grad : nullptr, status);
+                           flags, dfields, p->nf, partial, pfail);
+    hipLaunchKernelGGL(batched_finalize_kernel, dim3((unsigned)((int64_t)p->nf * p->ntheta)), dim3(kFinalizeThreads),
+                       0, s, partial, pfail, dfields, p->ntheta, thetas, out, p->grad ? grad : nullptr, status);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
 
-}  // namespace
-
-extern "C" {
-
-int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
-                        vecchia_plan **plan) {
-    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
-    return vecchia_plan_create_cov(fields, nf, ntheta, &cov, with_grad, plan);
+template <class V>
+void append_words(std::vector<uint64_t> &table, size_t byte_off, const V *data, size_t count) {
+    const size_t bytes = sizeof(V) * count;
+    const size_t words = (byte_off + bytes + 7) / 8;
+    if (table.size() < words) table.resize(words, 0);
+    std::copy((const char *)data, (const char *)data + bytes, (char *)table.data() + byte_off);
 }
 
-int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov,
-                            int32_t with_grad, vecchia_plan **plan) {
+// Host-side planning: no device memory, no streams, no synchronisation.
+int plan_build(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov, int32_t with_grad,
+               vecchia_plan **plan) {
     if (!plan) return VECCHIA_EINVAL;
     *plan = nullptr;
     double alpha = 1.0;
     const int kc = cov_code(cov, &alpha);
     if (!fields || nf < 1 || ntheta < 1 || kc < 0) return VECCHIA_EINVAL;
     if (nf > VECCHIA_MAX_FIELDS) return VECCHIA_EUNSUPPORTED;
+    if ((int64_t)nf * ntheta > (int64_t)INT32_MAX) return VECCHIA_EUNSUPPORTED;  // one finalize block per evaluation
     for (int32_t f = 0; f < nf; ++f) {
         const vecchia_field &F = fields[f];
         if (F.n < 0 || F.m < 0) return VECCHIA_EINVAL;
         if (F.m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
         if (F.n > 0 && (!F.locs || !F.z)) return VECCHIA_EINVAL;
         if (F.n > 1 && F.m > 0 && !F.nbr) return VECCHIA_EINVAL;
+        if (F.n > (int64_t)INT32_MAX * kChunk) return VECCHIA_EUNSUPPORTED;
     }
     vecchia_plan *p = new (std::nothrow) vecchia_plan();
     if (!p) return VECCHIA_EINVAL;
@@ -200,83 +212,53 @@ int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t nth
         d.nbr = fields[f].nbr;
         d.n = fields[f].n;
         d.m = fields[f].m;
-        d.eval0 = f * ntheta;
+        d.eval0 = (int64_t)f * ntheta;
         d.vals0 = rows;
-        p->fields.push_back(d);
-        for (int32_t q = 0; q < ntheta; ++q) {
-            EvalDev e{};
-            e.vals0 = rows + (int64_t)q * d.n;
-            e.n = d.n;
-            e.pb0 = pblocks;
-            e.nb = num_reduce_blocks(d.n);
-            pblocks += e.nb;
-            p->evals.push_back(e);
-        }
+        d.pb0 = pblocks;
+        d.nb = num_reduce_blocks(d.n);
+        pblocks += (int64_t)ntheta * d.nb;
         rows += (int64_t)ntheta * d.n;
+        p->fields.push_back(d);
     }
     p->total_rows = rows;
     p->total_pblocks = pblocks;
-    // tile classes, largest first so the longest launch starts first
+    if (pblocks > (int64_t)INT32_MAX) {
+        delete p;
+        return VECCHIA_EUNSUPPORTED;
+    }
+    // tile classes, largest first; within a class, fields by descending m
     for (int T = (VECCHIA_MAX_M + 2 + 15) / 16; T >= 1; --T) {
         ClassPlan C;
         C.T = T;
+        for (int32_t f = 0; f < nf; ++f)
+            if (tile_rows(fields[f].m) == T && fields[f].n > 0) C.fidx.push_back(f);
+        if (C.fidx.empty()) continue;
+        std::stable_sort(C.fidx.begin(), C.fidx.end(),
+                         [&](int32_t x, int32_t y) { return fields[x].m > fields[y].m; });
         C.item0.push_back(0);
-        for (int32_t f = 0; f < nf; ++f) {
-            if (tile_rows(fields[f].m) != T || fields[f].n == 0) continue;
-            C.fidx.push_back(f);
+        for (int32_t f : C.fidx) {
             C.item0.push_back(C.item0.back() + (int64_t)ntheta * fields[f].n);
             C.m_max = std::max(C.m_max, fields[f].m);
         }
-        if (C.fidx.empty()) continue;
         C.variant = resolve_variant(C.m_max, p->grad, 0);
         p->classes.push_back(C);
     }
-    // device tables
-    size_t off = 0;
-    p->off_fields = off;
-    off = align256(off + sizeof(FieldDev) * p->fields.size());
-    p->off_evals = off;
-    off = align256(off + sizeof(EvalDev) * p->evals.size());
+    // device table: the field array, then per class its field list and item offsets
+    size_t off = align256(sizeof(FieldDev) * p->fields.size());
     for (ClassPlan &C : p->classes) {
         C.off_fidx = off;
         off = align256(off + sizeof(int32_t) * C.fidx.size());
         C.off_item0 = off;
         off = align256(off + sizeof(int64_t) * C.item0.size());
     }
-    std::vector<char> host(off, 0);
-    std::copy((const char *)p->fields.data(), (const char *)(p->fields.data() + p->fields.size()),
-              host.data() + p->off_fields);
-    std::copy((const char *)p->evals.data(), (const char *)(p->evals.data() + p->evals.size()),
-              host.data() + p->off_evals);
+    p->table.assign(off / 8, 0);
+    append_words(p->table, 0, p->fields.data(), p->fields.size());
     for (const ClassPlan &C : p->classes) {
-        std::copy((const char *)C.fidx.data(), (const char *)(C.fidx.data() + C.fidx.size()), host.data() + C.off_fidx);
-        std::copy((const char *)C.item0.data(), (const char *)(C.item0.data() + C.item0.size()),
-                  host.data() + C.off_item0);
+        append_words(p->table, C.off_fidx, C.fidx.data(), C.fidx.size());
+        append_words(p->table, C.off_item0, C.item0.data(), C.item0.size());
     }
-    if (hipMalloc((void **)&p->d_buf, std::max<size_t>(off, 256)) != hipSuccess ||
-        hipMemcpy(p->d_buf, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
-        plan_release(p);
-        return VECCHIA_EHIP;
-    }
-    // streams and events for running the classes concurrently (default priority)
-    for (size_t c = 1; c < p->classes.size(); ++c) {
-        hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            plan_release(p);
-            return VECCHIA_EHIP;
-        }
-        p->streams.push_back(st);
-    }
-    for (size_t c = 0; c < std::max<size_t>(p->classes.size(), 1); ++c) {
-        hipEvent_t ev;
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-            plan_release(p);
-            return VECCHIA_EHIP;
-        }
-        p->events.push_back(ev);
-    }
-    // workspace layout
-    size_t w = 0;
+    // workspace layout: table, per-row values and flags, reduce partials
+    size_t w = off;
     p->ws_vals = w;
     w = align256(w + (size_t)rows * 4 * sizeof(double));
     p->ws_flags = w;
@@ -288,6 +270,21 @@ int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t nth
     p->ws_bytes = w + 256;
     *plan = p;
     return VECCHIA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vecchia_plan_create(const vecchia_field *fields, int32_t nf, int32_t ntheta, double nu, int32_t with_grad,
+                        vecchia_plan **plan) {
+    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
+    return plan_build(fields, nf, ntheta, &cov, with_grad, plan);
+}
+
+int vecchia_plan_create_cov(const vecchia_field *fields, int32_t nf, int32_t ntheta, const vecchia_cov *cov,
+                            int32_t with_grad, vecchia_plan **plan) {
+    return plan_build(fields, nf, ntheta, cov, with_grad, plan);
 }
 
 size_t vecchia_plan_workspace_size(const vecchia_plan *plan) { return plan ? plan->ws_bytes : 0; }
@@ -307,13 +304,36 @@ int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_r
 
 int vecchia_plan_destroy(vecchia_plan *plan) {
     if (!plan) return VECCHIA_EINVAL;
-    plan_release(plan);
+    delete plan;
     return VECCHIA_OK;
 }
 
-int vecchia_loglik_batched(const vecchia_plan *plan, const double *thetas, double *out, double *grad,
-                           int64_t *status, void *ws, size_t ws_bytes, void *stream) {
+int vecchia_plan_loglik(const vecchia_plan *plan, const double *thetas, double *out, double *grad, int64_t *status,
+                        void *ws, size_t ws_bytes, void *stream) {
     return run_batched(plan, thetas, out, grad, status, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t vecchia_batched_workspace(const vecchia_field *fields, int32_t nf, int32_t ntheta) {
+    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, 0.5};
+    vecchia_plan *p = nullptr;
+    if (plan_build(fields, nf, ntheta, &cov, 0, &p) != VECCHIA_OK) return 0;
+    const size_t bytes = p->ws_bytes;
+    delete p;
+    return bytes;
+}
+
+int vecchia_loglik_batched(const vecchia_field *fields, int32_t nf, const double *thetas, int32_t ntheta, double nu,
+                           int32_t with_grad, double *out, double *grad, int64_t *status, void *ws, size_t ws_bytes,
+                           void *stream) {
+    const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
+    vecchia_plan *p = nullptr;
+    const int rc = plan_build(fields, nf, ntheta, &cov, with_grad, &p);
+    if (rc != VECCHIA_OK) return rc;
+    // the launches carry everything they need in their arguments: the host
+    // plan can go as soon as they are enqueued
+    const int rc2 = run_batched(p, thetas, out, grad, status, ws, ws_bytes, (hipStream_t)stream);
+    delete p;
+    return rc2;
 }
 
 int vecchia_batched_graph_create(const vecchia_plan *plan, const double *thetas, double *out, double *grad,

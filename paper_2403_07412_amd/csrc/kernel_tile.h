@@ -1,6 +1,7 @@
 // Tiled kernel: one workgroup of W wavefronts per conditional, the augmented
 // block held in registers as 16x16 tiles, the Cholesky blocked by tile
-// columns with its trailing updates on FP64 matrix cores.
+// columns with its trailing updates on FP64 matrix cores and its triangular
+// solves by substitution.
 //
 // Block layout (same augmented block as the unblocked kernel): rows 0..k-1
 // neighbours, row k the point itself, row k+1 the observations, rows k+2..
@@ -8,25 +9,31 @@
 // k+1, the two forward solves of Algorithm 1 (POTRF + 2 TRSV, fused).
 //
 // Register tiles.  v_mfma_f64_16x16x4f64 leaves D[4r + l/16][l%16] in
-// accumulator register r of lane l.  Every tile M of the block is kept in
-// the transposed form of that layout ("T-layout"): lane (g, j) = (l/16, l%16),
-// register r holds M[j][4r + g].  With the inner index of a product taken as
-// kk = 4s + g in instruction s, a T-layout tile is directly the B operand of
-// M' M^T-style products and the panel operands need no transposes:
-//   TRSM  X^T = Linv A^T     A operand Linv[m][4s+g] (Linv in T-layout),
-//                            B operand register s of the tile itself;
-//   SYRK  A^T -= X_C X_R^T   both operands register s of the panel tiles.
-// The result of each product lands again in T-layout.
+// accumulator register r of lane l, and every tile M of the block is kept in
+// that layout ("N-layout"): lane (g, n) = (l/16, l%16), register r holds
+// M[4r + g][n].  The transposed form ("T-layout", register r of lane (g, j)
+// holding M[j][4r + g]) is the one panel tiles take in LDS, because as
+// either MFMA operand a T-layout tile X enters a product directly:
+//   SYRK   A_RC -= X_R X_C^T   operands -X_R and X_C, register s of each,
+//                              accumulating straight into the N-layout tile;
+// and an N-layout tile passed as the first operand enters as its transpose,
+// which is what the back substitution of the gradient needs (L_tC^T x).
 //
 // Per tile column t:
-//   1. the owner of the diagonal tile factors it (16 columns, one row per lane,
-//      64-bit DPP row broadcasts) and forms its inverse Linv_t (columns split
-//      over the four lane groups, which yields Linv_t in T-layout directly);
-//   2. owners of the tiles below apply X = A Linv_t^T (4 MFMAs per tile) and
-//      publish X to the LDS panel;
-//   3. owners of the trailing tiles subtract X_R X_C^T (4 MFMAs per tile).
-// Gradient: the same back substitution as the unblocked kernel, by tiles:
-//   x_t = Linv_t^T q_t, then q_C -= L_tC^T x_t for the tiles left of t.
+//   1. the owner of the diagonal tile factors it (one row per lane, 64-bit
+//      DPP row broadcasts) and publishes the strictly lower factor and the
+//      inverse pivots;
+//   2. the owners of the tiles below solve X L_tt^T = A in registers by
+//      forward substitution over the 16 columns (column c of an N-layout
+//      tile lives in lane c of every 16-lane row, so each step is one DPP
+//      broadcast FMA per register), and publish X to LDS in T-layout;
+//   3. the owners of the trailing tiles subtract X_R X_C^T (4 MFMAs per
+//      tile), the next diagonal tile first, so that its factorisation
+//      overlaps the other updates of the column.
+// Gradient: back substitution with L^T by tiles: x_t = L_tt^-T q_t by
+// substitution (one wave), then q_C -= L_tC^T x_t on the matrix cores for
+// the tiles of row t.  No step multiplies by an explicit inverse, so every
+// solve is backward stable, as in the unblocked kernel.
 #pragma once
 
 #include <type_traits>
@@ -45,37 +52,68 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr int tile_count(int T) { return T * (T + 1) / 2; }
 __host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_count(T) + W - 1) / W; }
 
+// LDS layout of the tiled kernel, in doubles.  The great-circle codes add
+// cos(latitude) of every row at the end; the other offsets do not depend on it.
+//
+// CUR[t % NPAR] receives diagonal tile t before its factorisation (row-major,
+// row stride 17) and then its strictly lower factor, with 1 / L_jj in
+// column 16 and again, contiguous, after the 16 x 17 block.  With several waves the buffer alternates by the parity of t:
+// the one tile t + 1 is stored into served column t - 1, whose readers all
+// passed a workgroup barrier since.  One array of T slots (DS doubles each)
+// serves both the panel and, with the gradient, the factored diagonal tiles:
+// while column t is processed, slot R > t holds the panel tile X_R (T-layout,
+// lane-major), and slot t' <= t holds factor t' in the CUR format, copied
+// there once every reader of X_t' has passed a barrier.
+template <int T, int W, bool GRAD, bool GCD = false>
+struct TileLds {
+    static constexpr int KP = 16 * T;
+    static constexpr int DS = 288;                        // a 16 x 17 tile, then 16 inverse pivots
+    static constexpr int NPAR = (W > 1 && T > 1) ? 2 : 1;
+    static constexpr int CUR = 0;                         // [NPAR][DS]  diagonal tile / its factor
+    static constexpr int SLOT = CUR + NPAR * DS;          // [T][DS]     panel tiles / stored factors
+    static constexpr int XY = SLOT + T * DS;              // [KP][2]     coordinates
+    static constexpr int ZV = XY + 2 * KP;                // [KP]        observations
+    static constexpr int YP = ZV + KP;                    // [KP]        factor row k+1
+    static constexpr int Q = YP + KP;                     // [KP][2]     back-substitution right-hand sides (gradient)
+    static constexpr int UB = Q + (GRAD ? 2 * KP : 0);    // [KP][2]     solutions (u, b) (gradient)
+    static constexpr int SCAL = UB + (GRAD ? 2 * KP : 0); // [16]        scalars: [0] L_kk
+    static constexpr int RED = SCAL + 16;                 // [2][32]     reductions (two values, up to 8 waves x 4 rows)
+    static constexpr int EXPT = RED + 64;                 // [64][2]     2^(j/64) as hi, lo for exp_neg_tab
+    static constexpr int CL = EXPT + 2 * kExpTableSize;   // [KP]        cos(latitude) (great-circle codes only)
+    static constexpr int TOTAL = CL + (GCD ? KP : 0);
+    static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
+};
+
+// TileLds<T, W, grad, gcd>::TOTAL, for the occupancy estimate.
+__host__ __device__ constexpr int tile_lds_doubles(int T, int W, bool grad, bool gcd) {
+    return ((W > 1 && T > 1) ? 2 : 1) * 288 + T * 288 + 16 * T * (4 + (grad ? 4 : 0) + (gcd ? 1 : 0)) + 16 + 64 +
+           2 * kExpTableSize;
+}
+static_assert(TileLds<8, 4, true, false>::TOTAL == tile_lds_doubles(8, 4, true, false), "LDS estimate out of date");
+static_assert(TileLds<3, 1, false, true>::TOTAL == tile_lds_doubles(3, 1, false, true), "LDS estimate out of date");
+
+// Shapes measured faster with one more workgroup per CU than the register
+// estimate below allows, at the price of a small spill: T = 8, W = 4 (m from
+// 110 to 125), value + gradient 67.0 ms at four workgroups (11 VGPRs spilled)
+// against 79.3 ms at three for the 10^6-point, m = 120 field; a fifth
+// workgroup (102 VGPRs) spilled more and took 91 ms.  Other shapes keep the
+// estimate.
+__host__ __device__ constexpr bool tile_measured_raise(int T, int W, bool gcd) { return T == 8 && W == 4 && !gcd; }
+
 // Occupancy target (wavefronts per SIMD) the register allocation aims at.
 // Workgroups per CU are limited by LDS and by registers: each lane holds 8
-// VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 96
-// for the diagonal factorisation, the covariance code and addressing.  Two
-// shapes were measured to need about 64 more and get that allowance.
-__host__ __device__ constexpr int tile_extra_vgprs(int T, int W) {
-    return ((T == 5 && W == 4) || (T == 7 && W == 8)) ? 64 : 0;
-}
-
-// One more workgroup per CU is worth a few spilled registers: the kernel is
-// bound by the latency of each conditional's dependency chain, and one more
-// resident workgroup hides more of it than the spill code costs, as long as
-// each wave keeps at least 102 VGPRs (5 wavefronts per SIMD).  Measured at
-// m = 120 (T = 8, W = 4, value + gradient): 40 VGPRs spilled for a fourth
-// workgroup, 8 % faster; W = 2 with 72 spilled for a fifth was 40 % slower,
-// and W = 8 at 6 wavefronts per SIMD (85 VGPRs) lost up to a third.
-constexpr int kTileSpillAllowance = 40;
-constexpr int kTileMaxRaisedWaves = 5;
-
-__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool gcd = false) {
-    const int lds = ((T + (T > 1 ? 2 : 1)) * 256 + 272 + (gcd ? 9 : 8) * 16 * T + 80 + 2 * kExpTableSize) * 8;  // TileLds::BYTES
+// VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 72
+// for the diagonal factorisation, the covariance code and addressing (the
+// compiler reports 143 VGPRs for T = 8, W = 4 with the gradient, nine tiles).
+__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool grad, bool gcd = false) {
+    const int lds = tile_lds_doubles(T, W, grad, gcd) * 8;
     const int blocks_lds = 163840 / lds;
-    const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 96 + tile_extra_vgprs(T, W);
+    const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 72 + (gcd ? 16 : 0);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
     const int blocks_regs = (wps_regs * 4) / W;      // workgroups per CU the registers allow
     int blocks = blocks_lds < blocks_regs ? blocks_lds : blocks_regs;
     if (blocks < 1) blocks = 1;
-    if (blocks + 1 <= blocks_lds) {                  // one more, if LDS allows and the spill stays small
-        const int wps1 = ((blocks + 1) * W + 3) / 4;
-        if (wps1 <= kTileMaxRaisedWaves && need - 512 / wps1 <= kTileSpillAllowance) blocks += 1;
-    }
+    if (!keep_d && tile_measured_raise(T, W, gcd) && blocks + 1 <= blocks_lds) blocks += 1;
     int wps = (blocks * W + 3) / 4;
     if (wps < 1) wps = 1;
     if (wps > 8) wps = 8;
@@ -83,43 +121,19 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d,
 }
 
 // Whether the gradient keeps the beta-derivative tiles in registers (one
-// exponential per entry) or recomputes them after the solves: kept only when
-// the extra registers cost no occupancy.
+// covariance evaluation per entry) or recomputes them after the solves.  For
+// the Matern codes on Euclidean distances an evaluation is about 32
+// instructions, and the tiles are kept only when the extra registers cost no
+// occupancy.  The great-circle codes spend two sines, an arcsine and (power
+// exponential) a logarithm and an exponential per entry: there the tiles are
+// kept whenever two wavefronts per SIMD still fit (measured: the 250,000-point
+// great-circle power-exponential gradient took 11.7 ms keeping them at two
+// wavefronts per SIMD, 17.0 ms recomputing at three).
 __host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
-    return VECCHIA_KEEP_DBETA && tile_waves_per_simd(T, W, true, gcd) >= tile_waves_per_simd(T, W, false, gcd);
+    return VECCHIA_KEEP_DBETA &&
+           (tile_waves_per_simd(T, W, true, true, gcd) >= tile_waves_per_simd(T, W, false, true, gcd) ||
+            (gcd && tile_waves_per_simd(T, W, true, true, gcd) >= 2));
 }
-
-// LDS layout of the tiled kernel, in doubles.  The great-circle codes add
-// cos(latitude) of every row at the end; the other offsets do not depend on it.
-//
-// One array of T tile slots serves both the panel and the stored inverses:
-// while column t is processed, slot R > t holds the panel tile X_R, and
-// slot t' <= t holds Linv_t' in N-layout (gradient only), written once the
-// last TRSM of column t' is done.  A slot never holds both at once.  The
-// factorisation publishes Linv_t for the TRSM in T-layout to CUR[t % 2]:
-// the buffer it overwrites served column t - 2, whose readers all passed a
-// workgroup barrier since.  A single tile column needs one such buffer.
-template <int T, bool GCD = false>
-struct TileLds {
-    static constexpr int KP = 16 * T;
-    static constexpr int NCUR = T > 1 ? 2 : 1;
-    static constexpr int CUR = 0;                   // [NCUR][64 lanes][4] Linv_t of the current column, T-layout
-    static constexpr int SLOT = CUR + NCUR * 256;   // [T][64 lanes][4]   panel X_R (slot R > t), Linv_t N-layout (slot t)
-    static constexpr int DIAG = SLOT + T * 256;     // [16][17]           diagonal tile, row-major
-    static constexpr int XY = DIAG + 272;           // [KP][2]            coordinates
-    static constexpr int ZV = XY + 2 * KP;          // [KP]               observations
-    static constexpr int YP = ZV + KP;              // [KP]               factor row k+1
-    static constexpr int Q = YP + KP;               // [KP][2]            back-substitution right-hand sides
-    static constexpr int UB = Q + 2 * KP;           // [KP][2]            solutions (u, b)
-    static constexpr int SCAL = UB + 2 * KP;        // [16]               scalars: [0] L_kk
-    static constexpr int RED = SCAL + 16;           // [2][32]            reductions (two values, up to 8 waves x 4 rows)
-    static constexpr int EXPT = RED + 64;           // [64][2]            2^(j/64) as hi, lo for exp_neg_tab
-    static constexpr int CL = EXPT + 2 * kExpTableSize;  // [KP]         cos(latitude) (great-circle codes only)
-    static constexpr int TOTAL = CL + (GCD ? KP : 0);
-    static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
-    static_assert(TOTAL == (T + NCUR) * 256 + 272 + (GCD ? 9 : 8) * KP + 80 + 2 * kExpTableSize,
-                  "occupancy estimate out of date");
-};
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
 // the tiles still active after step t form a prefix and a round-robin owner
@@ -204,7 +218,6 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
     return fma(y * e, p, y);
 }
 
-
 // 64-bit DPP move of both halves of a double (any DPP control).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -265,28 +278,26 @@ __device__ __forceinline__ double augment_value(int a, int b, int k, double v, c
     return v;
 }
 
-// Stores a diagonal tile (T-layout registers) row-major into the DIAG area.
-template <int T>
-__device__ __forceinline__ void store_diag(const dvec4 &v, double *smem) {
-    const int l = threadIdx.x % kWave, g = l / 16, j = l % 16;
+// Stores an N-layout tile (lane (g, n), register r: M[4r + g][n]) row-major
+// with row stride 17 at D.
+__device__ __forceinline__ void store_rowmajor17(const dvec4 &v, double *D) {
+    const int l = threadIdx.x % kWave, g = l / 16, n = l % 16;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) smem[TileLds<T>::DIAG + j * 17 + 4 * r + g] = v[r];
+    for (int r = 0; r < 4; ++r) D[(4 * r + g) * 17 + n] = v[r];
 }
 
-// Copies Linv_t from CUR[t % 2] in T-layout (lane (g, j), register r:
-// Linv[j][4r + g]) to slot t in N-layout (lane (g, n), register r:
-// Linv[4r + g][n]), by the wave that owns it.
-template <int T>
-__device__ __forceinline__ void linv_to_nlayout(int t, double *smem) {
-    const int l = threadIdx.x % kWave, g = l / 16, j = l % 16;
-    const dvec4 v = *reinterpret_cast<const dvec4 *>(smem + TileLds<T>::CUR + (t & 1) * 256 + l * 4);
-    double *Lt = smem + TileLds<T>::SLOT + t * 256;
+// Writes an N-layout tile to a panel slot in T-layout, lane-major: the reader
+// lane (g', j) finds M[j][4r' + g'] at slot[(16 g' + j) 4 + r'].  Element
+// (4r + g, n) of this lane goes to reader lane (n % 4, 4r + g), register n / 4.
+__device__ __forceinline__ void store_panel_tlayout(const dvec4 &v, double *slot) {
+    const int l = threadIdx.x % kWave, g = l / 16, n = l % 16;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Lt[(16 * (j % 4) + 4 * r + g) * 4 + j / 4] = v[r];
+    for (int r = 0; r < 4; ++r) slot[(16 * (n % 4) + 4 * r + g) * 4 + n / 4] = v[r];
 }
 
-// Factors diagonal tile t, which the calling wave has stored row-major in the
-// DIAG area of LDS; publishes Linv_t (T-layout, lane-major) to CUR[t % 2] and records L_kk
+// Factors diagonal tile t, which the calling wave has stored row-major (stride
+// 17) in D, in place: row j of D becomes the strictly lower part of row j of
+// the factor (zeros from column j on) and D[j][16] = 1 / L_jj.  Records L_kk
 // and the part of factor row k+1 that falls in this tile.  Every row is
 // factored: the padding rows have pivot 1 and the observation row's diagonal
 // is 2^600 (augment_value), so their pivots are positive and nothing past row
@@ -294,38 +305,26 @@ __device__ __forceinline__ void linv_to_nlayout(int t, double *smem) {
 // L_kk, and with it the conditional's value, into NaN, which the caller
 // reports.
 template <int T>
-__device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
-    using Ls = TileLds<T>;
+__device__ __forceinline__ void factor_diag(int t, int k, double *D, double *scal, double *yp) {
     int l = threadIdx.x % kWave;
     asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
     const int g = l / 16, j = l % 16;
-    double *S = smem + Ls::DIAG;  // the caller stored the tile here, row-major with stride 17
     // this wave is the critical path of the workgroup: let it win instruction
     // issue over the other waves sharing its SIMD while it factors
     __builtin_amdgcn_s_setprio(3);
     wave_lds_sync();
     double R[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) R[c] = S[j * 17 + c];
+    for (int c = 0; c < 16; ++c) R[c] = D[j * 17 + c];
     wave_lds_sync();
 
     const int base = 16 * t;
     const int jk = k - base;      // local index of row k (point i) if it lies in this tile
     const int jy = k + 1 - base;  // local index of row k+1 (observations) if it lies in this tile
-    // Linv is built row by row alongside the factor.  Lane (g, j) keeps
-    // W_j[4r + g] (r = 0..3), row j of the unit-scaled inverse: once column q
-    // is known, W_j -= (L[j][q] / L[q][q]) W_q for the rows j below q, with
-    // W_q broadcast from lane q; finally Linv[j][.] = W_j / L[j][j].  The
-    // result is Linv in T-layout.
-    double Wr[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Wr[r] = (j == 4 * r + g) ? 1.0 : 0.0;
-    double myinv = 1.0;  // 1 / L[j][j], kept per lane as column j passes
+    double myinv = 1.0;           // 1 / L[j][j], kept per lane as column j passes
     static_for<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         const double piv = bcast_row<q>(R[q]);
-        // no branch here: the pivot chain of the next column can then overlap
-        // the trailing update of this one
         const double inv = rsqrt_refined(piv);
         // column q of L: L[j][q] below the diagonal, L[q][q] = piv inv in
         // lane q; the entries above the diagonal are never read
@@ -341,27 +340,82 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *smem) {
         // take the select here: sunk to the end it would keep all 16
         // inverses live through the factorisation
         asm volatile("" : "+v"(myinv));
-        const double nlq_inv = (j > q) ? -(lq * inv) : 0.0;  // -L[j][q] / L[q][q]
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (r == 0) fma_bcast_row_self<q, true>(Wr[r], nlq_inv);
-            else fma_bcast_row_self<q, false>(Wr[r], nlq_inv);
-        }
     });
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Wr[r] *= myinv;
     // L_kk = 1 / (its refined reciprocal square-root pivot), within an ulp of
     // pivot * rsqrt(pivot)
-    if (g == 0 && base <= k && k < base + 16 && j == jk) smem[Ls::SCAL + 0] = 1.0 / myinv;
+    if (g == 0 && j == jk) scal[0] = 1.0 / myinv;
     if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-            if (c < jy) smem[Ls::YP + base + c] = R[c];
+            if (c < jy) yp[base + c] = R[c];
     }
-    double *Li = smem + Ls::CUR + (t & 1) * 256 + l * 4;
+    // publish: the four row groups hold the same rows and write a quarter of
+    // the columns each
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Li[r] = Wr[r];
+    for (int c = 0; c < 16; ++c)
+        if (c % 4 == g) D[j * 17 + c] = (c < j) ? R[c] : 0.0;
+    if (g == 0) D[j * 17 + 16] = myinv;
+    if (g == 1) D[272 + j] = myinv;
     __builtin_amdgcn_s_setprio(0);
+}
+
+// Forward substitution X L^T = A for the N-layout tiles x[0..P) held in
+// registers (row a of a tile in register a / 4 of row group a % 4, column n
+// in lane n): with the strictly lower factor Ls and the inverse pivots in D
+// (the CUR format), column c is final at step c, and column n > c loses
+// A[.][c] L[n][c] / L[c][c].  Column c of every row group sits in lane c of
+// that row, so each step is one DPP broadcast FMA per register; the inverse
+// pivots scale the columns at the end.  Backward stable like any triangular
+// substitution (no explicit inverse).  The weights of four steps are loaded
+// while the previous four steps run.
+template <int P>
+__device__ __forceinline__ void panel_solve(dvec4 (&x)[P], const double *D) {
+    const int n = threadIdx.x % 16;
+    const double *Lrow = D + n * 17;  // row n of the strictly lower factor
+    const double *dinv = D + 272;     // 1 / L_cc, contiguous
+    double la[4], da[4], w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        la[q] = Lrow[q];
+        da[q] = dinv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = -(la[q] * da[q]);
+    double xs[P][4];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xs[p][r] = x[p][r];
+    static_for<0, 4>([&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        if constexpr (G < 3) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                la[q] = Lrow[4 * G + 4 + q];
+                da[q] = dinv[4 * G + 4 + q];
+            }
+        }
+        static_for<0, 4>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int c = 4 * G + q;
+            static_for<0, P>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                // the first DPP read of a register follows its write by at least three instructions,
+                // except at the very first step
+                fma_bcast_row_self<c, c == 0 && p == 0>(xs[p][0], w[q]);
+                fma_bcast_row_self<c, false>(xs[p][1], w[q]);
+                fma_bcast_row_self<c, false>(xs[p][2], w[q]);
+                fma_bcast_row_self<c, false>(xs[p][3], w[q]);
+            });
+        });
+        if constexpr (G < 3) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = -(la[q] * da[q]);
+        }
+    });
+    const double dn = dinv[n];
+#pragma unroll
+    for (int p = 0; p < P; ++p) x[p] = dvec4{xs[p][0] * dn, xs[p][1] * dn, xs[p][2] * dn, xs[p][3] * dn};
 }
 
 // One conditional (modes as lds_conditional: qloc == NULL for the
@@ -371,11 +425,12 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                                     const int32_t *__restrict__ nbr, int64_t i, int64_t n, int32_t m,
                                     const double *qloc, const Params &P, double *smem) {
     constexpr bool GCD = kc_gcd(KC);
-    using Ls = TileLds<T, GCD>;
+    using Ls = TileLds<T, W, GRAD, GCD>;
     constexpr int NT = W * kWave;
     constexpr int NTW = tiles_per_wave(T, W);
     constexpr int NTILES = tile_count(T);
     constexpr int KP = Ls::KP;
+    constexpr int DS = Ls::DS;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int l = tid % kWave;
@@ -435,11 +490,12 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     }
     __syncthreads();
 
-    // covariance generation straight into the register tiles.  Only tiles
-    // that reach past row k (the observation row and the identity padding)
-    // and diagonal tiles (the nugget) need per-entry cases; the branches on
-    // them are uniform over the wavefront.  With the gradient, dC/dbeta is
-    // kept in dtile from the same exponential when registers allow.
+    // covariance generation straight into the N-layout register tiles: lane
+    // (g, n) register r of tile (R, C) is entry (16R + 4r + g, 16C + n).
+    // Only tiles that reach past row k (the observation row and the identity
+    // padding) and diagonal tiles (the nugget) need per-entry cases; the
+    // branches on them are uniform over the wavefront.  With the gradient,
+    // dC/dbeta is kept in dtile from the same exponential when registers allow.
     constexpr bool KEEP_D = GRAD && keep_dbeta(T, W, GCD);
     const double *ET = smem + Ls::EXPT;
     dvec4 tile[NTW];
@@ -451,26 +507,26 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         if constexpr (KEEP_D) dtile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
         const int R_ = SR(s), C_ = SC(s);
         if (R_ < 0) continue;
-        const int a = 16 * R_ + j;
-        const double xa = XY[2 * a], ya = XY[2 * a + 1], ca = GCD ? CLv[a] : 0.0;
+        const int b = 16 * C_ + j;
+        const double xb = XY[2 * b], yb = XY[2 * b + 1], cb = GCD ? CLv[b] : 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int b = 16 * C_ + 4 * r + g;
+            const int a = 16 * R_ + 4 * r + g;
             double cv, db;
-            cov_pair<KC, KEEP_D>(xa, ya, ca, XY[2 * b], XY[2 * b + 1], GCD ? CLv[b] : 0.0, P, s2b, ET, cv, db);
+            cov_pair<KC, KEEP_D>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv, db);
             tile[s][r] = cv;
             if constexpr (KEEP_D) dtile[s][r] = db;
         }
         if (R_ == C_) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (a == 16 * C_ + 4 * r + g) tile[s][r] += P.tau2;
+                if (16 * R_ + 4 * r + g == b) tile[s][r] += P.tau2;
         }
         if (16 * R_ + 15 > k) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tile[s][r] = augment_value(a, 16 * C_ + 4 * r + g, k, tile[s][r], Z);
+            for (int r = 0; r < 4; ++r) tile[s][r] = augment_value(16 * R_ + 4 * r + g, b, k, tile[s][r], Z);
         }
-        if (R_ == 0 && C_ == 0) store_diag<T>(tile[s], smem);
+        if (R_ == 0 && C_ == 0) store_rowmajor17(tile[s], smem + Ls::CUR);
     }
 
     // blocked right-looking Cholesky
@@ -481,68 +537,59 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // loop, which at this register budget spill to scratch
         int lo = l * 4;
         asm volatile("" : "+v"(lo));
-        // 1. diagonal tile t: fully updated, and stored to DIAG by its owner
-        if (w == tile_index(T, t, t) % W) factor_diag<T>(t, k, smem);
+        double *D = smem + Ls::CUR + (Ls::NPAR == 2 ? (t & 1) : 0) * DS;
+        const bool diag_owner = w == tile_index(T, t, t) % W;
+        // 1. diagonal tile t (fully updated, stored to D by its owner)
+        if (diag_owner) factor_diag<T>(t, k, D, smem + Ls::SCAL, smem + Ls::YP);
         __syncthreads();
-        // 2. tiles below: X = A Linv_t^T, published to the panel (T-layout).
-        // With the gradient the register copy is kept in N-layout (the same
-        // product with the operands swapped), the form the back substitution
-        // feeds to the matrix cores.
-        const double *Li = smem + Ls::CUR + (t & 1) * 256 + lo;
+        // the factor goes to slot t for the back substitution: the panel tile
+        // X_t it replaces was last read by the trailing update of column t - 1
+        if constexpr (GRAD) {
+            if (diag_owner) {
+                double *St = smem + Ls::SLOT + t * DS;
+                for (int e = l; e < DS; e += kWave) St[e] = D[e];
+            }
+        }
+        // 2. tiles below: X = A L_t^-T by substitution, kept in registers
+        // (N-layout, the factor tile itself) and published in T-layout
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
             if (SC(s) == t && SR(s) > t) {
-                const dvec4 li = *reinterpret_cast<const dvec4 *>(Li);
-                dvec4 acc = {0.0, 0.0, 0.0, 0.0};
-                dvec4 accn = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], tile[s][q], acc, 0, 0, 0);
-                    if constexpr (GRAD) accn = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], li[q], accn, 0, 0, 0);
-                }
-                *reinterpret_cast<dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + lo) = acc;
-                tile[s] = GRAD ? accn : acc;
+                dvec4 one[1] = {tile[s]};
+                panel_solve<1>(one, D);
+                tile[s] = one[0];
+                store_panel_tlayout(tile[s], smem + Ls::SLOT + SR(s) * DS);
             }
         }
         __syncthreads();
-        // Linv_t has served its last TRSM: the back substitution wants it in
-        // N-layout, copied by its owner to slot t (its panel tile X_t was
-        // last read by the trailing update of column t - 1, before the
-        // barriers above)
-        if constexpr (GRAD) {
-            if (w == tile_index(T, t, t) % W) linv_to_nlayout<T>(t, smem);
-        }
-        // 3. trailing update of the tiles right of column t
+        // 3. trailing update of the tiles right of column t, the next diagonal
+        // tile first: it is then handed to the factorisation
+        double *Dn = smem + Ls::CUR + (Ls::NPAR == 2 ? ((t + 1) & 1) : 0) * DS;
 #pragma unroll
-        for (int s = 0; s < NTW; ++s) {
-            if (SC(s) > t) {
-                const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * 256 + lo);
-                const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * 256 + lo);
+        for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xc[q], xr[q], tile[s], 0, 0, 0);
-                // the next diagonal tile is now final: hand it to the factorisation
-                if (SR(s) == t + 1 && SC(s) == t + 1) store_diag<T>(tile[s], smem);
+            for (int s = 0; s < NTW; ++s) {
+                const bool nextdiag = SR(s) == t + 1 && SC(s) == t + 1;
+                if (SC(s) > t && (pass == 0) == nextdiag) {
+                    const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * DS + lo);
+                    const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * DS + lo);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xr[q], xc[q], tile[s], 0, 0, 0);
+                    if (nextdiag) store_rowmajor17(tile[s], Dn);
+                }
             }
         }
     }
-    // observation row k+1 from the tiles left of its diagonal tile: in
-    // T-layout lane (g, jy) holds it, in N-layout register jy/4 of the lanes
-    // of row group jy%4
+    // observation row k+1 from the tiles left of its diagonal tile: row jy of
+    // an N-layout tile is register jy / 4 of row group jy % 4
     const int ty = (k + 1) / 16, jy = (k + 1) % 16;
 #pragma unroll
     for (int s = 0; s < NTW; ++s) {
         if (SR(s) == ty && SC(s) < ty) {
-            if constexpr (GRAD) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (4 * r + g == jy) smem[Ls::YP + 16 * SC(s) + j] = tile[s][r];
-            } else {
-                if (j == jy) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) smem[Ls::YP + 16 * SC(s) + 4 * r + g] = tile[s][r];
-                }
-            }
+            for (int r = 0; r < 4; ++r)
+                if (4 * r + g == jy) smem[Ls::YP + 16 * SC(s) + j] = tile[s][r];
         }
     }
     __syncthreads();
@@ -559,15 +606,14 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const double c = Lkk * Lkk;
         const double rr = wv / Lkk;
         const double half = 0.5 * (rr * rr - 1.0 / c);
-        // back substitution with L^T for both right-hand sides at once, on
-        // the matrix cores.  A 16 x 16 operand in N-layout (lane (g, n),
-        // register r holds M[4r + g][n]) enters a product as M^T when passed
-        // first and as M when passed second, and the product comes out in
-        // N-layout.  With the right-hand sides as columns 0 and 1 of X:
-        // x_t = Linv_t^T q_t, then q_C -= L_tC^T x_t for the tiles of row t;
-        // x_t leaves the first product already laid out as the second
-        // operand of the next.  Every wave forms x_t itself, so one barrier
-        // per step suffices.  Q holds (q_u, q_b) pairs, UB receives (u, b).
+        // back substitution with L^T for both right-hand sides at once.  Q
+        // holds (q_u, q_b) pairs, UB receives (u, b).  Per tile row t, from
+        // the last: the owner of the diagonal tile solves L_tt^T x_t = q_t by
+        // substitution (lanes of row groups 0 and 1 hold the two right-hand
+        // sides, lane n entry n), then the owners of the tiles (t, C), C < t,
+        // subtract L_tC^T x_t from q_C on the matrix cores: an N-layout tile
+        // as the first operand enters as its transpose, and x_t as the second
+        // operand sits in lanes (g, j < 2), register q holding x_j[4q + g].
         double *Q = smem + Ls::Q, *UB = smem + Ls::UB;
         const double *YP = smem + Ls::YP;
         for (int t = tid; t < KP; t += NT) {
@@ -575,35 +621,64 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             Q[2 * t + 1] = (t == k) ? Lkk : 0.0;
         }
         __syncthreads();
-        const bool rhs_lane = j < 2;  // lanes of columns 0 and 1
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
-            int qo = 2 * g + j;  // opaque per step, as in the factorisation loop
-            asm volatile("" : "+v"(qo));
-            const dvec4 li = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + t * 256 + l * 4);
-            dvec4 xq;
+            const double *St = smem + Ls::SLOT + t * DS;  // strictly lower L_tt, 1 / L_jj in column 16
+            if (w == tile_index(T, t, t) % W) {
+                double qv = (g < 2) ? Q[2 * (16 * t + j) + g] : 0.0;
+                // column c from the last: x_c = q_c / L_cc, then q_n -= L_cn x_c (n < c);
+                // weights -L[c][n] / L[c][c] (zero for n >= c), four steps loaded ahead
+                double la[4], da[4], wg[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xq[q] = rhs_lane ? Q[2 * (16 * t + 4 * q + g) + j] : 0.0;
-            dvec4 x = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) x = __builtin_amdgcn_mfma_f64_16x16x4f64(li[q], xq[q], x, 0, 0, 0);
-            if (w == tile_index(T, t, t) % W && rhs_lane) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) UB[2 * (16 * t + 4 * r + g) + j] = x[r];
-            }
-#pragma unroll
-            for (int s = 0; s < NTW; ++s) {
-                if (SR(s) == t && SC(s) < t) {
-                    dvec4 d = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) d = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], x[q], d, 0, 0, 0);
-                    if (rhs_lane) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) Q[32 * SC(s) + 8 * r + qo] -= d[r];
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    la[q] = St[(15 - q) * 17 + j];
+                    da[q] = St[272 + 15 - q];
                 }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) wg[q] = -(la[q] * da[q]);
+                static_for<0, 4>([&](auto gc) {
+                    constexpr int G = decltype(gc)::value;
+                    if constexpr (G < 3) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            la[q] = St[(11 - 4 * G - q) * 17 + j];
+                            da[q] = St[272 + 11 - 4 * G - q];
+                        }
+                    }
+                    static_for<0, 4>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        fma_bcast_row_self<15 - 4 * G - q, true>(qv, wg[q]);
+                    });
+                    if constexpr (G < 3) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) wg[q] = -(la[q] * da[q]);
+                    }
+                });
+                if (g < 2) UB[2 * (16 * t + j) + g] = qv * St[272 + j];
             }
             __syncthreads();
+            if (t > 0) {
+                int qo = 2 * g + j;  // opaque per step, as in the factorisation loop
+                asm volatile("" : "+v"(qo));
+                const bool rhs_lane = j < 2;
+                dvec4 xq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xq[q] = rhs_lane ? UB[2 * (16 * t + 4 * q + g) + j] : 0.0;
+#pragma unroll
+                for (int s = 0; s < NTW; ++s) {
+                    if (SR(s) == t && SC(s) < t) {
+                        dvec4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            d = __builtin_amdgcn_mfma_f64_16x16x4f64(tile[s][q], xq[q], d, 0, 0, 0);
+                        if (rhs_lane) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) Q[32 * SC(s) + 8 * r + qo] -= d[r];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
         }
         // dl/dtau2 = u^T b; dl/dbeta = sum_{a > b} D_ab (u_a b_b + u_b b_a).
         // u and b vanish past row k, so entries there add exact zeros; in a
@@ -617,36 +692,36 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         for (int s = 0; s < NTW; ++s) {
             const int R_ = SR(s), C_ = SC(s);
             if (R_ < 0 || 16 * R_ > k) continue;
-            const int a = 16 * R_ + j;
-            const double2 uba = *reinterpret_cast<const double2 *>(UB + 2 * a);
+            const int b = 16 * C_ + j;
+            const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * b);
             dvec4 db4;
             if constexpr (KEEP_D) {
                 db4 = dtile[s];
             } else {
-                const double xa = XY[2 * a], ya = XY[2 * a + 1], ca = GCD ? CLv[a] : 0.0;
+                const double xb = XY[2 * b], yb = XY[2 * b + 1], cb = GCD ? CLv[b] : 0.0;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int b = 16 * C_ + 4 * r + g;
+                    const int a = 16 * R_ + 4 * r + g;
                     double cv, db;
-                    cov_pair<KC, true>(xa, ya, ca, XY[2 * b], XY[2 * b + 1], GCD ? CLv[b] : 0.0, P, s2b, ET, cv,
+                    cov_pair<KC, true>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv,
                                        db);
                     db4[r] = db;
                 }
             }
-            double w = 1.0;
+            double wt = 1.0;
             if (R_ == C_) {  // wave-uniform: only diagonal tiles hold a == b
-                w = 0.5;
+                wt = 0.5;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (a == 16 * C_ + 4 * r + g) db4[r] = 0.0;
+                    if (16 * R_ + 4 * r + g == b) db4[r] = 0.0;
             }
             double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double2 ubb = *reinterpret_cast<const double2 *>(UB + 2 * (16 * C_ + 4 * r + g));
+                const double2 uba = *reinterpret_cast<const double2 *>(UB + 2 * (16 * R_ + 4 * r + g));
                 acc = fma(db4[r], fma(uba.x, ubb.y, ubb.x * uba.y), acc);
             }
-            gb = fma(w, acc, gb);
+            gb = fma(wt, acc, gb);
         }
         block_sum2<W>(ub, gb, smem + Ls::RED);
         o.g2 = ub;

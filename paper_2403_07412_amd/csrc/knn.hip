@@ -18,13 +18,18 @@
 // haversine value on the same grid, with a haversine lower bound for the
 // unscanned rings.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <stdint.h>
 
 #include <algorithm>
 #include <cmath>
 
+#include "sort.h"
 #include "vecchia.h"
+
+using vecchia::exclusive_scan_i32;
+using vecchia::radix_sort_pairs;
+using vecchia::radix_sort_temp_bytes;
+using vecchia::scan_temp_bytes;
 
 namespace {
 
@@ -546,12 +551,7 @@ struct KnnLayout {
 };
 
 size_t knn_temp_bytes(int64_t n, int64_t cells) {
-    size_t sort_bytes = 0, scan_bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)n);
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, (const int32_t *)nullptr, (int32_t *)nullptr,
-                                           (int)(cells + 1));
-    return std::max(sort_bytes, scan_bytes);
+    return std::max(radix_sort_temp_bytes<uint32_t>(n), scan_temp_bytes(cells + 1));
 }
 
 KnnLayout knn_layout(int64_t n) {
@@ -591,11 +591,8 @@ MortonLayout morton_layout(int64_t n) {
     L.val = o;    o += align256(sizeof(int32_t) * nn);
     L.skey = o;   o += align256(sizeof(uint32_t) * nn);
     L.sval = o;   o += align256(sizeof(int32_t) * nn);
-    size_t sort_bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)nn);
-    L.temp_bytes = sort_bytes;
-    L.temp = o;   o += align256(sort_bytes);
+    L.temp_bytes = radix_sort_temp_bytes<uint32_t>((int64_t)nn);
+    L.temp = o;   o += align256(L.temp_bytes);
     L.total = o;
     return L;
 }
@@ -628,11 +625,8 @@ MaxminLayout maxmin_layout(int64_t n) {
     L.skey = o;   o += align256(sizeof(uint64_t) * nn);
     L.sval = o;   o += align256(sizeof(int32_t) * nn);
     L.count = o;  o += 256;
-    size_t sort_bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                             (const int32_t *)nullptr, (int32_t *)nullptr, (int)nn);
-    L.temp_bytes = sort_bytes;
-    L.temp = o;   o += align256(sort_bytes);
+    L.temp_bytes = radix_sort_temp_bytes<uint64_t>((int64_t)nn);
+    L.temp = o;   o += align256(L.temp_bytes);
     L.total = o;
     return L;
 }
@@ -677,12 +671,10 @@ int knn_run(const double *locs, int64_t n, const double *qlocs, int64_t nq, int3
         hipLaunchKernelGGL(cell_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, gp, L.g, key, val,
                            count);
         if (hipGetLastError() != hipSuccess) return VECCHIA_EHIP;
-        size_t tb = L.temp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(temp, tb, key, skey, val, sval, (int)n, 0, bits_for(L.cells), s) !=
-            hipSuccess)
+        if (radix_sort_pairs<uint32_t>(temp, L.temp_bytes, (const uint32_t *)key, (uint32_t *)skey, val, sval, n, 0,
+                                       bits_for(L.cells), s) != hipSuccess)
             return VECCHIA_EHIP;
-        tb = L.temp_bytes;
-        if (hipcub::DeviceScan::ExclusiveSum(temp, tb, count, cstart, (int)(L.cells + 1), s) != hipSuccess)
+        if (exclusive_scan_i32(temp, L.temp_bytes, count, cstart, L.cells + 1, s) != hipSuccess)
             return VECCHIA_EHIP;
         hipLaunchKernelGGL(gather_sorted_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, sval,
                            (const double *)clat, sxy, sclat);
@@ -746,8 +738,59 @@ extern "C" int vecchia_morton_order(const double *locs, int64_t n, int64_t *perm
     hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(kBoxBlocks), 0, s, part, 0, gp);
     hipLaunchKernelGGL(morton_code_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, locs, n, gp, key, val);
     if (hipGetLastError() != hipSuccess) return VECCHIA_EHIP;
-    size_t tb = L.temp_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(base + L.temp, tb, key, skey, val, sval, (int)n, 0, 32, s) != hipSuccess)
+    if (radix_sort_pairs<uint32_t>(base + L.temp, L.temp_bytes, key, skey, val, sval, n, 0, 32, s) != hipSuccess)
+        return VECCHIA_EHIP;
+    hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, sval, n, perm);
+    return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+}
+
+// ---- random ordering ----------------------------------------------------------
+
+namespace {
+
+__global__ void random_key_kernel(int64_t n, uint64_t seed, uint64_t *__restrict__ key, int32_t *__restrict__ val) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        key[i] = mix64(seed ^ (uint64_t)i);
+        val[i] = (int32_t)i;
+    }
+}
+
+struct RandomLayout {
+    size_t key, val, skey, sval, temp, total, temp_bytes;
+};
+
+RandomLayout random_layout(int64_t n) {
+    RandomLayout L{};
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t o = 0;
+    L.key = o;    o += align256(sizeof(uint64_t) * nn);
+    L.val = o;    o += align256(sizeof(int32_t) * nn);
+    L.skey = o;   o += align256(sizeof(uint64_t) * nn);
+    L.sval = o;   o += align256(sizeof(int32_t) * nn);
+    L.temp_bytes = radix_sort_temp_bytes<uint64_t>((int64_t)nn);
+    L.temp = o;   o += align256(L.temp_bytes);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+extern "C" size_t vecchia_random_order_workspace_size(int64_t n) { return random_layout(n < 0 ? 0 : n).total; }
+
+extern "C" int vecchia_random_order(int64_t n, uint64_t seed, int64_t *perm, void *ws, size_t ws_bytes,
+                                    void *stream) {
+    if (n < 0 || n > INT32_MAX) return VECCHIA_EINVAL;
+    if (n == 0) return VECCHIA_OK;
+    if (!perm) return VECCHIA_EINVAL;
+    const RandomLayout L = random_layout(n);
+    if (!ws || ws_bytes < L.total) return VECCHIA_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    uint64_t *key = (uint64_t *)(base + L.key), *skey = (uint64_t *)(base + L.skey);
+    int32_t *val = (int32_t *)(base + L.val), *sval = (int32_t *)(base + L.sval);
+    hipLaunchKernelGGL(random_key_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, seed, key, val);
+    if (radix_sort_pairs<uint64_t>(base + L.temp, L.temp_bytes, key, skey, val, sval, n, 0, 64, s) != hipSuccess)
         return VECCHIA_EHIP;
     hipLaunchKernelGGL(widen_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, sval, n, perm);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
@@ -800,8 +843,7 @@ extern "C" int vecchia_maxmin_order(const double *locs, int64_t n, uint64_t seed
             hipStreamSynchronize(s) != hipSuccess)
             return VECCHIA_EHIP;
         if (cnt <= 0 || done + cnt > n) return VECCHIA_EHIP;  // every round elects at least one point
-        size_t tb = L.temp_bytes;
-        if (hipcub::DeviceRadixSort::SortPairs(base + L.temp, tb, key, skey, val, sval, cnt, 0, 64, s) !=
+        if (radix_sort_pairs<uint64_t>(base + L.temp, L.temp_bytes, key, skey, val, sval, cnt, 0, 64, s) !=
             hipSuccess)
             return VECCHIA_EHIP;
         hipLaunchKernelGGL(append_kernel, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, (const int32_t *)sval,

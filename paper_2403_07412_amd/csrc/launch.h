@@ -38,32 +38,38 @@ struct TileImpl {
     static constexpr bool GCD = kc_gcd(KC);
     static constexpr int WPE = VECCHIA_WPE_OVERRIDE > 0
                                    ? VECCHIA_WPE_OVERRIDE
-                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD), GCD);
-    static size_t smem(int) { return TileLds<T, GCD>::BYTES; }
+                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD), GRAD, GCD);
+    static size_t smem(int) { return TileLds<T, W, GRAD, GCD>::BYTES; }
     static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int64_t n,
                                   int32_t m, const double *qloc, const Params &P, double *sm) {
         return tile_conditional<T, W, KC, GRAD>(locs, z, nbr, i, n, m, qloc, P, sm);
     }
 };
 
-// A field of a batched evaluation, as the device sees it.
+// A field of a batched evaluation, as the device sees it (a table the
+// batched entry points write into the caller's workspace).
 struct FieldDev {
     const double *locs;   // [n][2]
     const double *z;      // [n]
     const int32_t *nbr;   // [n][m]
     int64_t n;
-    int32_t m;
-    int32_t eval0;        // evaluation index of (this field, theta 0); evaluation e = field * ntheta + theta
+    int64_t m;
+    int64_t eval0;        // evaluation index of (this field, theta 0); evaluation e = field * ntheta + theta
     int64_t vals0;        // row of (this field, theta 0, point 0) in the per-point value array
+    int64_t pb0;          // first reduce block of (this field, theta 0); theta q owns [pb0 + q nb, + nb)
+    int64_t nb;           // reduce blocks per evaluation of this field
 };
 
 // Arguments of one conditional-kernel launch (passed by value).
 //   single mode (fields == NULL): item t is point idx[t] (or t) of one field;
-//     results go to ell[t * ell_stride], g[t * g_stride + 0..2], flags[t] or status;
+//     results go to row t - row0 of ell (ell[row * ell_stride]), g
+//     (g[row * g_stride + 0..2]) and flags, or to status;
 //   batched mode: the items of a tile class, t in [0, item0[nfc]); item t lies
-//     in class field c (item0[c] <= t < item0[c+1]) = fields[fidx[c]], with
-//     theta index p and point i from t - item0[c] = p n + i; results go to row
-//     vals0 + p n + i of ell / g / flags, parameters to theta + 3 (eval0 + p);
+//     in class field c (item0[c] <= t < item0[c+1]) = fields[fidx[c]]; with
+//     r = t - item0[c], the point is i = n - 1 - r / ntheta (items run from the
+//     last point, whose conditioning set is full, to the first) and the theta
+//     index q = r % ntheta; results go to row vals0 + q n + i of ell / g /
+//     flags, parameters come from theta + 3 (eval0 + q);
 //   prediction mode (qlocs != NULL, single mode only): item t is prediction
 //     point t < nq at qlocs[t], conditioned on row t of nbr among the n
 //     points of locs / z; mean and variance go to pmean[t], pvar[t].
@@ -79,6 +85,7 @@ struct KernelArgs {
     const int32_t *fidx;
     const int64_t *item0;
     int32_t nfc;
+    int32_t ntheta;
     double *ell;
     int64_t ell_stride;
     double *g;
@@ -86,20 +93,18 @@ struct KernelArgs {
     int32_t *flags;
     unsigned long long *status;
     int64_t t0;
+    int64_t row0;  // single mode: results of item t go to row t - row0
     double alpha;
     const double *qlocs;
     int64_t nq;
     double *pmean, *pvar;
 };
 
-// One workgroup per item (a point of one evaluation).  Failure is reported
-// through flags[row] (when given) or as atomicMin(status, t + 1) (when given);
-// failed rows hold NaN.
+// Evaluates item t (see KernelArgs) with one workgroup.  Failure is reported
+// through flags[row] (when given) or as atomicMin(status, t + 1) (when
+// given); failed rows hold NaN.
 template <class Impl>
-__global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(Impl::WPE)))
-    cond_kernel(const KernelArgs a) {
-    extern __shared__ double smem[];
-    const int64_t t = a.t0 + blockIdx.x;
+__device__ __forceinline__ void cond_item(const KernelArgs &a, int64_t t, double *smem) {
     const double *locs = a.locs, *z = a.z, *theta = a.theta;
     const int32_t *nbr = a.nbr;
     int64_t n = a.n, i, row;
@@ -116,15 +121,16 @@ __global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(I
         z = F.z;
         nbr = F.nbr;
         n = F.n;
-        m = F.m;
+        m = (int32_t)F.m;
         const int64_t r = t - a.item0[lo];
-        const int64_t p = r / n;
-        i = r - p * n;
-        theta = a.theta + 3 * ((int64_t)F.eval0 + p);
-        row = F.vals0 + r;
+        const int64_t ip = r / a.ntheta;
+        const int64_t q = r - ip * a.ntheta;
+        i = n - 1 - ip;
+        theta = a.theta + 3 * (F.eval0 + q);
+        row = F.vals0 + q * n + i;
     } else {
         i = a.idx ? a.idx[t] : t;
-        row = t;
+        row = t - a.row0;
     }
     const Params P = load_params(theta, a.alpha);
     const bool pred = a.qlocs != nullptr;
@@ -151,6 +157,16 @@ __global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(I
         if (a.flags) a.flags[row] = bad ? 1 : 0;
         if (a.status && bad && P.valid) atomicMin(a.status, (unsigned long long)(t + 1));
     }
+}
+
+// One workgroup per item.  (A persistent form, workgroups pulling items from
+// a counter, kept about 25 more VGPRs and twice the scalar spills live across
+// its loop in the T = 8, W = 4 kernel, one workgroup per CU less: slower.)
+template <class Impl>
+__global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(Impl::WPE)))
+    cond_kernel(const KernelArgs a) {
+    extern __shared__ double smem[];
+    cond_item<Impl>(a, a.t0 + blockIdx.x, smem);
 }
 
 template <typename K>

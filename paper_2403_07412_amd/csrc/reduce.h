@@ -23,13 +23,15 @@ __host__ __device__ inline int64_t num_reduce_blocks(int64_t n) {
     return (n + kPointsPerReduceBlock - 1) / kPointsPerReduceBlock;
 }
 
-// Level 1 for reduce block bx of a segment: vals [n][4], flags [n];
-// writes partial[0..8) (four double-double pairs) and *pfail (first failing
-// point + 1 in the block, or kNoFailure).  Called by every thread of a
-// kReduceThreads-thread block.
+// Level 1 for reduce block bx of a segment: point i's row is i - row0 of
+// vals [.][4] and flags [.] (row0 > 0 when the rows hold a slice of the
+// segment that starts at point row0); writes partial[0..8) (four
+// double-double pairs) and *pfail (first failing point + 1 in the block, or
+// kNoFailure).  Called by every thread of a kReduceThreads-thread block.
 __device__ __forceinline__ void reduce_segment_block(const double *__restrict__ vals,
                                                      const int32_t *__restrict__ flags, int64_t n, int64_t bx,
-                                                     double *__restrict__ partial, int64_t *__restrict__ pfail) {
+                                                     double *__restrict__ partial, int64_t *__restrict__ pfail,
+                                                     int64_t row0 = 0) {
     __shared__ DD sh[4][kReduceThreads];
     __shared__ int64_t shf[kReduceThreads];
     const int t = threadIdx.x;
@@ -37,11 +39,12 @@ __device__ __forceinline__ void reduce_segment_block(const double *__restrict__ 
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int64_t f = kNoFailure;
     for (int64_t i = i0; i < i0 + kChunk && i < n; ++i) {
-        a0 += vals[4 * i + 0];
-        a1 += vals[4 * i + 1];
-        a2 += vals[4 * i + 2];
-        a3 += vals[4 * i + 3];
-        if (flags[i] && f == kNoFailure) f = i + 1;
+        const int64_t r = i - row0;
+        a0 += vals[4 * r + 0];
+        a1 += vals[4 * r + 1];
+        a2 += vals[4 * r + 2];
+        a3 += vals[4 * r + 3];
+        if (flags[r] && f == kNoFailure) f = i + 1;
     }
     sh[0][t] = DD{a0, 0.0};
     sh[1][t] = DD{a1, 0.0};

@@ -81,3 +81,70 @@ def test_variant_table_roundtrip_on_host(tmp_path, lib):
     v.vecchia_set_variant(60, True, "auto")
     with pytest.raises(v.VecchiaError):
         v.vecchia_set_variant(150, True, "tile_w1")
+
+
+def _fake_fields(v, specs):
+    """Field descriptors with dummy device addresses: planning never dereferences them."""
+    arr = (v._Field * len(specs))()
+    for f, (n, m) in enumerate(specs):
+        arr[f] = v._Field(0x10000, 0x20000, 0x30000, n, m)
+    return arr
+
+
+def test_batched_workspace_query_and_plan_are_host_only(lib):
+    import paper_2403_07412_amd as v
+    specs = [(10_000, 10), (200_000, 60), (1, 30), (0, 5), (50_000, 150)]
+    arr = _fake_fields(v, specs)
+    need = lib.vecchia_batched_workspace(arr, len(specs), 4)
+    # at least the per-row values and flags, 36 bytes per (field, theta, point)
+    assert need >= 36 * 4 * sum(n for n, _ in specs)
+    handle = ctypes.c_void_p()
+    cov = v.Cov(v.MATERN, v.EUCLIDEAN, 1.5)
+    assert lib.vecchia_plan_create_cov(arr, len(specs), 4, ctypes.byref(cov), 1, ctypes.byref(handle)) == 0
+    try:
+        assert lib.vecchia_plan_workspace_size(handle) == need
+        classes = lib.vecchia_plan_num_classes(handle)
+        assert classes == len({(m + 2 + 15) // 16 for n, m in specs if n > 0})
+        items = ctypes.c_int64()
+        total = 0
+        for c in range(classes):
+            assert lib.vecchia_plan_class_info(handle, c, None, None, None, ctypes.byref(items)) == 0
+            total += items.value
+        assert total == 4 * sum(n for n, _ in specs)
+    finally:
+        assert lib.vecchia_plan_destroy(handle) == 0
+
+
+def test_batched_rejects_oversized_batches_on_the_host(lib):
+    import paper_2403_07412_amd as v
+    arr = _fake_fields(v, [(10, 5), (10, 5)])
+    handle = ctypes.c_void_p()
+    # nf * ntheta evaluations must fit in 2^31 - 1
+    assert lib.vecchia_plan_create(arr, 2, 2 ** 31 - 1, ctypes.c_double(0.5), 0, ctypes.byref(handle)) == 2
+    assert lib.vecchia_batched_workspace(arr, 2, 2 ** 31 - 1) == 0
+    # m beyond the maximum, bad nu, no fields
+    big = _fake_fields(v, [(10, 161)])
+    assert lib.vecchia_plan_create(big, 1, 1, ctypes.c_double(0.5), 0, ctypes.byref(handle)) == 2
+    assert lib.vecchia_plan_create(arr, 2, 1, ctypes.c_double(0.7), 0, ctypes.byref(handle)) == 1
+    assert lib.vecchia_plan_create(arr, 0, 1, ctypes.c_double(0.5), 0, ctypes.byref(handle)) == 1
+    # the one-call form checks its arguments before any device work
+    P = ctypes.c_void_p
+    d = P(0x1000)
+    assert lib.vecchia_loglik_batched(arr, 2, d, 1, 0.5, 1, d, None, d, d, 1 << 30, None) == 1  # grad missing
+    assert lib.vecchia_loglik_batched(arr, 2, d, 1, 0.5, 0, d, None, d, d, 16, None) == 4      # workspace
+
+
+# Files of the likelihood path (single and batched evaluations, kernels, sums).
+LIKELIHOOD_SOURCES = ["vecchia.hip", "batched.hip", "launch.h", "kernel_tile.h", "kernel_lds.h", "reduce.h",
+                      "device_common.h"]
+
+
+def test_likelihood_path_never_allocates_or_creates_streams():
+    csrc = os.path.join(ROOT, "paper_2403_07412_amd", "csrc")
+    banned = re.compile(r"\b(hipMalloc\w*|hipExtMalloc\w*|hipHostMalloc|hipFree\w*|hipStreamCreate\w*|"
+                        r"hipMemcpy\w*|hipMemset\w*|hipDeviceSynchronize|hipStreamSynchronize)\b")
+    for name in LIKELIHOOD_SOURCES:
+        text = open(os.path.join(csrc, name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        hits = banned.findall(text)
+        assert not hits, (name, hits)

@@ -142,3 +142,58 @@ def test_autotune_sets_a_feasible_variant(v):
     assert all(t > 0 for t in times.values())
     assert min(times, key=times.get) == {val: k for k, val in v.VARIANTS.items()}[best]
     v.vecchia_set_variant(60, True, before)
+
+
+def test_one_call_form_equals_the_plan_bitwise(v):
+    """vecchia_loglik_batched (fields in a host array, no plan object) against vecchia_plan_loglik."""
+    import torch
+    rng = np.random.default_rng(81)
+    nu = 2.5
+    fields = make_fields(rng, [(900, 60), (0, 8), (1300, 17), (450, 100)], nu)
+    ntheta = 5
+    thetas = torch.from_numpy(random_thetas(rng, len(fields), ntheta)).cuda()
+    plan = v.BatchedPlan([f[1] for f in fields], ntheta, nu, True)
+    p_out, p_grad, p_status = plan(thetas)
+    assert v.vecchia_batched_workspace([f[1] for f in fields], ntheta) == plan.ws.numel()
+    for rep in range(2):  # the second call reuses nothing from the first
+        o, g, s = v.vecchia_loglik_batched([f[1] for f in fields], thetas, nu, True)
+        torch.cuda.synchronize()
+        assert torch.equal(o, p_out) and torch.equal(g, p_grad) and torch.equal(s, p_status), rep
+    assert (p_status == 0).all()
+    o2, g2, s2 = v.vecchia_loglik_batched([f[1] for f in fields], thetas, nu, False)
+    torch.cuda.synchronize()
+    assert g2 is None and torch.equal(o2, p_out) and (s2 == 0).all()
+    plan.close()
+
+
+def test_binding_rejects_mistyped_theta_and_outputs(v):
+    """A float32 theta or an int32 status would be read or written past its end through the raw pointer."""
+    import torch
+    rng = np.random.default_rng(82)
+    f, (locs, z, nbr, m) = make_fields(rng, [(200, 10)], 0.5)[0]
+    good = torch.tensor([1.0, 0.1, 1e-3], dtype=torch.float64, device="cuda")
+    with pytest.raises(TypeError):
+        v.vecchia_loglik_grad(locs, z, nbr, m, 0.5, good.float())
+    with pytest.raises(ValueError):
+        v.vecchia_loglik_grad(locs, z, nbr, m, 0.5, torch.ones(2, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        v.vecchia_loglik(locs, z, nbr, m, 0.5, good, status=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(TypeError):
+        v.vecchia_loglik_grad(locs, z, nbr, m, 0.5, good, out=torch.zeros(1, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        v.vecchia_loglik_grad(locs, z, nbr, m, 0.5, good, grad=torch.zeros(2, dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        v.loglik(locs, z, nbr, good.float().requires_grad_(True), 0.5, m)
+    with pytest.raises(TypeError):
+        v.vecchia_predict(locs, z, locs[:5].contiguous(), nbr[:5].contiguous(), m, (v.MATERN, v.EUCLIDEAN, 0.5),
+                          good.float())
+    plan = v.BatchedPlan([(locs, z, nbr, m)], 2, 0.5, True)
+    with pytest.raises(ValueError):
+        plan(torch.ones((1, 3, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(TypeError):
+        o, g, s = plan.outputs()
+        plan(torch.ones((1, 2, 3), dtype=torch.float64, device="cuda"), status=s.int())
+    plan.close()
+    out, st = v.vecchia_loglik(locs, z, nbr, m, 0.5, good)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and np.isfinite(out.item())

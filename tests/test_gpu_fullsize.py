@@ -4,7 +4,7 @@
   replayed from a captured graph, both against the oracle's total over all 10^6 conditionals
   (rel 1e-10 value, 1e-9 gradient), bitwise equal to each other, plus sampled per-point terms.
   Sampled terms agree to 1e-9; where an ill-conditioned term does not, a 50-digit evaluation decides
-  and the kernel's error must stay within a small factor of the FP64 oracle's (assert_adjudicated).
+  and the kernel's error must stay within 1.5 times the FP64 oracle's (assert_adjudicated).
 - n = 250,000 jittered grid, m = 60, nu = 3/2, value: the total against the oracle.
 - n = 200,000, m = 60, nu = 5/2, 64 parameter vectors with gradients in one batched launch: every
   vector bitwise equal to its own single call, four of them against the oracle's totals.
@@ -62,6 +62,7 @@ def check_terms(v, f, theta, L, Z, N, rows, with_grad):
         want = oracle.terms(f.locs, f.z, f.nbr, f.m, f.nu, theta, idx=rows, threads=THREADS)
     got = t.cpu().numpy()
     rel = np.abs(got - want) / np.maximum(1.0, np.abs(want))
+    print(f"{rows.size} sampled terms: max rel difference to the oracle {rel.max():.2e}", flush=True)
     off = np.argsort(rel)[::-1][:40]
     off = off[rel[off] > 1e-9]
     if not off.size:
@@ -75,10 +76,11 @@ def check_terms(v, f, theta, L, Z, N, rows, with_grad):
 
 def assert_adjudicated(parts):
     """Errors against the 50-digit values, pooled over every term that two FP64 evaluations disagreed
-    on.  The tiled kernels apply explicit inverses of their 16 x 16 diagonal tiles in the triangular
-    solves, which costs a small factor of accuracy against substitution: measured 3-4 times the plain
-    FP64 oracle's error on blocks with kappa near 1e7, where the unblocked kernel (substitution)
-    matches the oracle.  The pooled root-mean-square error may be 6 times the oracle's."""
+    on.  Every triangular solve of the kernels is a substitution, as in the oracle, so the kernel's
+    error must match the oracle's: the pooled root-mean-square error may be 1.5 times the oracle's.
+    (The tiled kernels once multiplied by explicit inverses of their 16 x 16 diagonal tiles and were
+    3-4 times less accurate on blocks with kappa near 1e7; with substitution no sampled term of the
+    full-size workloads differs from the oracle by more than 1e-9.)"""
     e_gpu = np.concatenate([p[0] for p in parts])
     e_orc = np.concatenate([p[1] for p in parts])
     exact = np.concatenate([p[2] for p in parts])
@@ -86,7 +88,7 @@ def assert_adjudicated(parts):
         return
     rg, ro = np.sqrt(np.mean(e_gpu ** 2)), np.sqrt(np.mean(e_orc ** 2))
     print(f"adjudicated {e_gpu.size} terms: rms error vs 50 digits kernel {rg:.3e}, oracle {ro:.3e}", flush=True)
-    assert rg <= 6.0 * ro + 1e-13 * np.sqrt(np.mean(exact ** 2))
+    assert rg <= 1.5 * ro + 1e-13 * np.sqrt(np.mean(exact ** 2))
     assert np.max(np.abs(e_gpu) / np.maximum(1.0, np.abs(exact))) <= 1e-6
 
 

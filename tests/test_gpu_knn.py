@@ -147,3 +147,38 @@ def test_query_and_maxmin_edge_cases(v):
     got = v.vecchia_maxmin_order(torch.from_numpy(locs).cuda(), seed=5).cpu().numpy()
     assert sorted(got) == list(range(500))
     assert v.vecchia_maxmin_order(empty).shape == (0,)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 5), (1023, 1), (1024, 1), (1025, 2), (300_001, 3), (2_000_000, 99)])
+def test_random_order_equals_the_oracle(v, n, seed):
+    """vecchia_random_order (device radix sort of 64-bit keys, 8 passes) against the oracle's sort."""
+    got = v.vecchia_random_order(n, seed=seed)
+    import torch
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), oracle.random_order(n, seed))
+
+
+def test_conditioning_sets_replay_from_a_graph(v):
+    """The neighbour search is kernel launches only (device sort and scan): captured once, every replay
+    gives the eager sets, with eager work between the replays."""
+    import torch
+    rng = np.random.default_rng(321)
+    n, m = 30_000, 40
+    locs = torch.from_numpy(rng.uniform(size=(n, 2))).cuda()
+    ws = torch.empty(v.vecchia_knn_workspace_size(n), dtype=torch.uint8, device="cuda")
+    out = torch.empty((n, m), dtype=torch.int32, device="cuda")
+    want = torch.from_numpy(oracle.knn_rows(locs.cpu().numpy(), m)).cuda()
+    v.vecchia_knn(locs, m, out=out, ws=ws)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        v.vecchia_knn(locs, m, out=out, ws=ws)
+    for rep in range(3):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), rep
+        junk = torch.randn(5000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
