@@ -378,6 +378,33 @@ def m_sweep_times(v, stream, n: int = 250_000, ms=(10, 30, 60, 90, 120, 150), nu
     return {"workload": f"n={n} uniform, Matern nu={nu}, value+gradient, m in {list(ms)}", "rows": rows}
 
 
+def mle_times(v, stream, n: int = 20_000, m: int = 30, nu: float = 1.5):
+    """Maximum-likelihood fit (Sec. V's use of the likelihood) of 20,000 uniform points, Matern 3/2, z ~ N(0, 1)
+    i.i.d.: the line search with one trial step per device round trip against four; same estimate, wall
+    time and round trips."""
+    import torch
+
+    rng = np.random.default_rng(7002)
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(rng.uniform(size=(n, 2))).to(dev)
+    Z = torch.from_numpy(rng.standard_normal(n)).to(dev)
+    N = v.vecchia_knn(L, m, stream=stream)
+    out = {}
+    for k in (1, 4):
+        opt = v.mle_default_options()
+        opt.trial_steps = k
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = v.vecchia_mle(L, Z, N, m, nu, (0.5, 0.3, 0.2), options=opt, stream=stream)
+        sec = time.perf_counter() - t0
+        out[f"trial_steps_{k}"] = {"seconds": sec, "iterations": r["iterations"], "evaluations": r["evaluations"],
+                                   "round_trips": r["round_trips"], "theta": [float(x) for x in r["theta"]],
+                                   "loglik": r["loglik"]}
+    out["workload"] = f"n={n} uniform, m={m}, Matern nu={nu}, z iid N(0,1), start (0.5, 0.3, 0.2)"
+    out["same_estimate"] = out["trial_steps_1"]["theta"] == out["trial_steps_4"]["theta"]
+    return out
+
+
 def multifield_times(v, stream, reps: int = 3):
     """The 32-field workload (n log-uniform in [1e4, 5e5], m uniform in 10..150, Matern nu = 3/2, one
     theta per field, value + gradient): 32 per-field calls with the built-in default variants against
@@ -617,6 +644,7 @@ def main():
         rec["grid_forward"] = grid_forward_times(v, stream)
         rec["multitheta"] = multitheta_times(v, stream)
         rec["m_sweep"] = m_sweep_times(v, stream)
+        rec["mle"] = mle_times(v, stream)
     if not args.no_preprocess:
         rec["preprocess"] = preprocess_times(v, f, locs, stream)
     if not args.no_realdata:

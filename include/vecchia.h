@@ -467,6 +467,7 @@ typedef struct vecchia_mle_options {
     double ftol;       /* default 1e-13 */
     double lower[3];   /* bounds on theta, 0 < lower <= upper, finite (defaults 1e-8, 1e-8, 1e-10) */
     double upper[3];   /* (defaults 1e8 each) */
+    int32_t trial_steps; /* step lengths the line search evaluates per device round trip, 1..8 (default 4) */
 } vecchia_mle_options;
 
 void vecchia_mle_default_options(vecchia_mle_options *opt);
@@ -479,21 +480,28 @@ size_t vecchia_mle_workspace_size(int64_t n, int32_t m);
  *   theta       [host] double[3] receives the estimate
  *   loglik      [host] double or NULL: l at the estimate
  *   grad        [host] double[3] or NULL: dl/dtheta at the estimate
- *   iterations, evaluations  [host] int32 or NULL
- *   ws          [dev] at least vecchia_mle_workspace_size(n, m) bytes
- * Synchronises the stream after every evaluation.  Returns VECCHIA_OK,
+ *   iterations, evaluations, round_trips  [host] int32 or NULL: iterations,
+ *               parameter vectors evaluated, device round trips (launch,
+ *               read-back and synchronisation)
+ *   ws          [dev] at least vecchia_mle_workspace_size(n, m) bytes, 256-byte aligned
+ * Each round trip evaluates a set of parameter vectors as the theta columns
+ * of one batched launch (a host plan over the field): the line search tries
+ * the next trial_steps halvings of the step at once and takes the longest
+ * that satisfies the Armijo condition, the step one-at-a-time backtracking
+ * would take.  Synchronises the stream once per round trip.  Returns VECCHIA_OK,
  * VECCHIA_EINVAL (bad arguments or options, or theta0 does not evaluate),
  * VECCHIA_EUNSUPPORTED, VECCHIA_EWORKSPACE or VECCHIA_EHIP.
  */
 int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                 const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
-                double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes, void *stream);
+                double *grad, int32_t *iterations, int32_t *evaluations, int32_t *round_trips, void *ws,
+                size_t ws_bytes, void *stream);
 
 /* vecchia_mle under any covariance model (smoothness fixed, as vecchia_loglik_cov). */
 int vecchia_mle_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                     const vecchia_cov *cov, const double *theta0, const vecchia_mle_options *options, double *theta,
-                    double *loglik, double *grad, int32_t *iterations, int32_t *evaluations, void *ws,
-                    size_t ws_bytes, void *stream);
+                    double *loglik, double *grad, int32_t *iterations, int32_t *evaluations, int32_t *round_trips,
+                    void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Exact Gaussian-process log-likelihood, Eq. (1), for the KL divergence of

@@ -47,7 +47,8 @@ class _Field(ctypes.Structure):
 class MleOptions(ctypes.Structure):
     """vecchia_mle_options."""
     _fields_ = [("max_iter", ctypes.c_int32), ("history", ctypes.c_int32), ("gtol", ctypes.c_double),
-                ("ftol", ctypes.c_double), ("lower", ctypes.c_double * 3), ("upper", ctypes.c_double * 3)]
+                ("ftol", ctypes.c_double), ("lower", ctypes.c_double * 3), ("upper", ctypes.c_double * 3),
+                ("trial_steps", ctypes.c_int32)]
 
 
 class VecchiaError(RuntimeError):
@@ -165,7 +166,7 @@ def _load():
         lib.vecchia_mle_cov.restype = ctypes.c_int
         lib.vecchia_mle_cov.argtypes = [P, P, P, I64, I32, CP, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
                                         ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
-                                        ctypes.POINTER(I32), P, SZ, P]
+                                        ctypes.POINTER(I32), ctypes.POINTER(I32), P, SZ, P]
         lib.vecchia_loglik_cov.restype = ctypes.c_int
         lib.vecchia_loglik_cov.argtypes = [P, P, P, I64, I32, CP, P, P, P, P, P, SZ, P]
         lib.vecchia_loglik_terms_cov.restype = ctypes.c_int
@@ -175,7 +176,7 @@ def _load():
         lib.vecchia_mle.restype = ctypes.c_int
         lib.vecchia_mle.argtypes = [P, P, P, I64, I32, D, ctypes.POINTER(D), ctypes.POINTER(MleOptions),
                                     ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
-                                    ctypes.POINTER(I32), P, SZ, P]
+                                    ctypes.POINTER(I32), ctypes.POINTER(I32), P, SZ, P]
         _lib = lib
     return _lib
 
@@ -828,7 +829,7 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
                 cov=None):
     """Maximum-likelihood (sigma2, beta, tau2) at fixed nu (Matern, Euclidean), or under the covariance
     model cov = (family, metric, smoothness) when given (then nu is ignored).  Returns a dict with theta,
-    loglik, grad, iterations and evaluations."""
+    loglik, grad, iterations, evaluations and round_trips (device launches with a read-back)."""
     n = _as_inputs(locs, z, nbr, m)
     c = _cov(cov if cov is not None else (MATERN, EUCLIDEAN, nu))
     need = int(_load().vecchia_mle_workspace_size(n, m))
@@ -840,12 +841,14 @@ def vecchia_mle(locs, z, nbr, m: int, nu: float, theta0, options: MleOptions = N
     ll = ctypes.c_double()
     it = ctypes.c_int32()
     ev = ctypes.c_int32()
+    trips = ctypes.c_int32()
     rc = _load().vecchia_mle_cov(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, int(m), ctypes.byref(c),
                                  th0, ctypes.byref(options) if options is not None else None, th, ctypes.byref(ll),
-                                 gr, ctypes.byref(it), ctypes.byref(ev), _ptr(ws), _nbytes(ws), _stream(stream))
+                                 gr, ctypes.byref(it), ctypes.byref(ev), ctypes.byref(trips), _ptr(ws), _nbytes(ws),
+                                 _stream(stream))
     _check(rc, "vecchia_mle")
     return {"theta": np.array(th[:]), "loglik": ll.value, "grad": np.array(gr[:]), "iterations": it.value,
-            "evaluations": ev.value}
+            "evaluations": ev.value, "round_trips": trips.value}
 
 
 # ------------------------------------------------------------- KL harness

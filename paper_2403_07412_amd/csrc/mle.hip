@@ -1,11 +1,18 @@
 // Maximum-likelihood estimation of (sigma2, beta, tau2) at fixed smoothness,
 // for any covariance model: the use the Vecchia log-likelihood is built for
-// (Sec. V fits the Matern and power-exponential parameters by maximising it).  The paper drives a derivative-free NLopt
-// search; here the fused value + gradient evaluation feeds a projected
-// limited-memory BFGS in log-parameters, phi = log theta, inside bounds.
+// (Sec. V fits the Matern and power-exponential parameters by maximising it).
+// The paper drives a derivative-free NLopt search; here the fused value +
+// gradient evaluation feeds a projected limited-memory BFGS in
+// log-parameters, phi = log theta, inside bounds.
 //
-// Host code only: every evaluation is one vecchia_loglik_cov call on the
-// caller's stream, followed by a 40-byte read-back and a stream sync.
+// Host code driving the batched evaluation: every device round trip
+// evaluates a set of parameter vectors as the theta columns of one host plan
+// (vecchia_plan_loglik, one launch per round trip), reads back their values,
+// gradients and statuses in one copy and synchronises once.  The line search
+// evaluates K = trial_steps step lengths (the next K halvings of the step)
+// per round trip and takes the longest one that satisfies the Armijo
+// condition, the step sequential backtracking would take, in about 1/K of
+// the round trips.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,7 +26,8 @@ namespace {
 
 constexpr int kNp = 3;            // sigma2, beta, tau2
 constexpr int kMaxHistory = 20;
-constexpr size_t kScratch = 256;  // device scratch at the front of ws: out, grad, status, theta
+constexpr int kMaxTrials = 8;     // step lengths per round trip, at most
+constexpr size_t kScratch = 2048; // device scratch at the front of ws: thetas, outputs, statuses of one round trip
 
 struct Eval {
     double f;          // -l / n (+inf when the evaluation failed)
@@ -29,45 +37,63 @@ struct Eval {
     bool ok;
 };
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 struct Problem {
-    const double *locs, *z;
-    const int32_t *nbr;
+    vecchia_plan *plan[kMaxTrials + 1] = {};  // plan[k]: k parameter vectors per launch, made when first needed
+    vecchia_field field{};
+    vecchia_cov cov{};
     int64_t n;
-    int32_t m;
-    vecchia_cov cov;
     char *ws;
     size_t ws_bytes;
     hipStream_t s;
-    int evals = 0;
+    int evals = 0, trips = 0;
 
-    int eval(const double *phi, Eval &e) {
-        double th[kNp];
-        for (int p = 0; p < kNp; ++p) th[p] = std::exp(phi[p]);
-        double *d_out = (double *)ws;
-        double *d_grad = d_out + 1;
-        int64_t *d_status = (int64_t *)(d_out + 4);
-        double *d_theta = d_out + 5;
-        if (hipMemcpyAsync(d_theta, th, sizeof(th), hipMemcpyHostToDevice, s) != hipSuccess) return VECCHIA_EHIP;
-        const int rc = vecchia_loglik_cov(locs, z, nbr, n, m, &cov, d_theta, d_out, d_grad, d_status, ws + kScratch,
-                                          ws_bytes - kScratch, s);
+    ~Problem() {
+        for (vecchia_plan *p : plan)
+            if (p) vecchia_plan_destroy(p);
+    }
+
+    // Evaluates the k parameter vectors phi[0..k) (log theta) in one launch and one round trip.
+    int eval(const double (*phi)[kNp], int k, Eval *e) {
+        double th[kMaxTrials][kNp];
+        for (int q = 0; q < k; ++q)
+            for (int p = 0; p < kNp; ++p) th[q][p] = std::exp(phi[q][p]);
+        double *d_theta = (double *)ws;                     // [k][3]
+        double *d_out = d_theta + 3 * kMaxTrials;           // [k]  then grad [k][3]
+        double *d_grad = d_out + kMaxTrials;
+        int64_t *d_status = (int64_t *)(d_grad + 3 * kMaxTrials);
+        if (!plan[k]) {
+            const int prc = vecchia_plan_create_cov(&field, 1, k, &cov, 1, &plan[k]);
+            if (prc != VECCHIA_OK) return prc;
+        }
+        if (hipMemcpyAsync(d_theta, th, sizeof(double) * kNp * k, hipMemcpyHostToDevice, s) != hipSuccess)
+            return VECCHIA_EHIP;
+        const int rc = vecchia_plan_loglik(plan[k], d_theta, d_out, d_grad, d_status, ws + kScratch,
+                                           ws_bytes - kScratch, s);
         if (rc != VECCHIA_OK) return rc;
-        double host[5];
-        int64_t status = 0;
-        if (hipMemcpyAsync(host, d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(&status, d_status, sizeof(status), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        // outputs, gradients and statuses are contiguous: one copy back
+        double host[kMaxTrials * 5];
+        if (hipMemcpyAsync(host, d_out, sizeof(double) * kMaxTrials * 5, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return VECCHIA_EHIP;
-        ++evals;
-        e.ll = host[0];
-        e.ok = status == 0 && std::isfinite(host[0]);
+        ++trips;
+        evals += k;
         const double scale = n > 0 ? 1.0 / (double)n : 1.0;
-        e.f = e.ok ? -host[0] * scale : INFINITY;
-        for (int p = 0; p < kNp; ++p) {
-            e.gth[p] = host[1 + p];
-            e.g[p] = -host[1 + p] * th[p] * scale;  // chain rule through theta = e^phi
-            e.ok = e.ok && std::isfinite(e.g[p]);
+        for (int q = 0; q < k; ++q) {
+            int64_t status;
+            std::memcpy(&status, &host[4 * kMaxTrials + q], sizeof(status));
+            Eval &x = e[q];
+            x.ll = host[q];
+            x.ok = status == 0 && std::isfinite(x.ll);
+            x.f = x.ok ? -x.ll * scale : INFINITY;
+            for (int p = 0; p < kNp; ++p) {
+                x.gth[p] = host[kMaxTrials + 3 * q + p];
+                x.g[p] = -x.gth[p] * th[q][p] * scale;  // chain rule through theta = e^phi
+                x.ok = x.ok && std::isfinite(x.g[p]);
+            }
+            if (!x.ok) x.f = INFINITY;
         }
-        if (!e.ok) e.f = INFINITY;
         return VECCHIA_OK;
     }
 };
@@ -92,23 +118,33 @@ extern "C" void vecchia_mle_default_options(vecchia_mle_options *opt) {
     opt->upper[0] = 1e8;
     opt->upper[1] = 1e8;
     opt->upper[2] = 1e8;
+    opt->trial_steps = 4;
 }
 
-extern "C" size_t vecchia_mle_workspace_size(int64_t n, int32_t m) { return kScratch + vecchia_workspace_size(n, m); }
+extern "C" size_t vecchia_mle_workspace_size(int64_t n, int32_t m) {
+    if (n < 0 || m < 0 || m > VECCHIA_MAX_M) return 0;
+    // the largest plan: one field with kMaxTrials parameter vectors
+    const vecchia_field f{(const double *)16, (const double *)16, (const int32_t *)16, n, m};
+    const size_t plan_ws = vecchia_batched_workspace(&f, 1, kMaxTrials);
+    return plan_ws ? kScratch + plan_ws : 0;
+}
 
 extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
                                const vecchia_cov *cov, const double *theta0, const vecchia_mle_options *options,
                                double *theta, double *loglik, double *grad, int32_t *iterations,
-                               int32_t *evaluations, void *ws, size_t ws_bytes, void *stream) {
+                               int32_t *evaluations, int32_t *round_trips, void *ws, size_t ws_bytes, void *stream) {
     if (!cov || !theta0 || !theta || !locs || !z || (m > 0 && !nbr) || n < 1 || m < 0) return VECCHIA_EINVAL;
+    if (m > VECCHIA_MAX_M) return VECCHIA_EUNSUPPORTED;
     vecchia_mle_options opt;
     if (options) {
         opt = *options;
     } else {
         vecchia_mle_default_options(&opt);
     }
-    if (opt.max_iter < 0 || opt.history < 1 || opt.history > kMaxHistory || !(opt.gtol >= 0) || !(opt.ftol >= 0))
+    if (opt.max_iter < 0 || opt.history < 1 || opt.history > kMaxHistory || !(opt.gtol >= 0) || !(opt.ftol >= 0) ||
+        opt.trial_steps < 1 || opt.trial_steps > kMaxTrials)
         return VECCHIA_EINVAL;
+    const int K = opt.trial_steps;
     double lo[kNp], hi[kNp], phi[kNp];
     for (int p = 0; p < kNp; ++p) {
         if (!(opt.lower[p] > 0) || !(opt.upper[p] >= opt.lower[p]) || !std::isfinite(opt.upper[p]) ||
@@ -118,11 +154,17 @@ extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_
         hi[p] = std::log(opt.upper[p]);
         phi[p] = std::min(hi[p], std::max(lo[p], std::log(theta0[p])));
     }
-    if (!ws || ws_bytes < vecchia_mle_workspace_size(n, m)) return VECCHIA_EWORKSPACE;
-    Problem pb{locs, z, nbr, n, m, *cov, (char *)ws, ws_bytes, (hipStream_t)stream};
+    if (!ws || ws_bytes < vecchia_mle_workspace_size(n, m) || ((uintptr_t)ws & 255) != 0) return VECCHIA_EWORKSPACE;
+    Problem pb;
+    pb.field = vecchia_field{locs, z, nbr, n, m};
+    pb.cov = *cov;
+    pb.n = n;
+    pb.ws = (char *)ws;
+    pb.ws_bytes = ws_bytes;
+    pb.s = (hipStream_t)stream;
 
     Eval cur;
-    int rc = pb.eval(phi, cur);
+    int rc = pb.eval(&phi, 1, &cur);
     if (rc != VECCHIA_OK) return rc;
     if (!cur.ok) return VECCHIA_EINVAL;  // the starting point itself does not evaluate
 
@@ -183,21 +225,32 @@ extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_
             for (int p = 0; p < kNp; ++p) dmax = std::max(dmax, std::fabs(d[p]));
             if (dmax > 1.0) step = 1.0 / dmax;
         }
-        // projected backtracking line search with the Armijo condition
+        // projected backtracking line search with the Armijo condition: the
+        // next K halvings of the step in one round trip, the longest
+        // acceptable one taken
         Eval nxt{};
         double phin[kNp];
         bool accepted = false;
-        for (int ls = 0; ls < 40; ++ls) {
-            for (int p = 0; p < kNp; ++p) phin[p] = std::min(hi[p], std::max(lo[p], phi[p] + step * d[p]));
-            double dphi[kNp];
-            for (int p = 0; p < kNp; ++p) dphi[p] = phin[p] - phi[p];
-            rc = pb.eval(phin, nxt);
+        for (int ls = 0; ls < 40 && !accepted; ls += K) {
+            const int k = std::min(K, 40 - ls);
+            double cand[kMaxTrials][kNp];
+            Eval ev[kMaxTrials];
+            double st = step;
+            for (int q = 0; q < k; ++q, st *= 0.5)
+                for (int p = 0; p < kNp; ++p) cand[q][p] = std::min(hi[p], std::max(lo[p], phi[p] + st * d[p]));
+            rc = pb.eval(cand, k, ev);
             if (rc != VECCHIA_OK) return rc;
-            if (nxt.ok && nxt.f <= cur.f + 1e-4 * dot(cur.g, dphi)) {
-                accepted = true;
-                break;
+            for (int q = 0; q < k; ++q) {
+                double dphi[kNp];
+                for (int p = 0; p < kNp; ++p) dphi[p] = cand[q][p] - phi[p];
+                if (ev[q].ok && ev[q].f <= cur.f + 1e-4 * dot(cur.g, dphi)) {
+                    std::memcpy(phin, cand[q], sizeof(phin));
+                    nxt = ev[q];
+                    accepted = true;
+                    break;
+                }
             }
-            step *= 0.5;
+            step = st;
         }
         if (!accepted) break;
         double s[kNp], y[kNp];
@@ -226,14 +279,15 @@ extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_
         for (int p = 0; p < kNp; ++p) grad[p] = cur.gth[p];
     if (iterations) *iterations = iter;
     if (evaluations) *evaluations = pb.evals;
+    if (round_trips) *round_trips = pb.trips;
     return VECCHIA_OK;
 }
 
 extern "C" int vecchia_mle(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m, double nu,
                            const double *theta0, const vecchia_mle_options *options, double *theta, double *loglik,
-                           double *grad, int32_t *iterations, int32_t *evaluations, void *ws, size_t ws_bytes,
-                           void *stream) {
+                           double *grad, int32_t *iterations, int32_t *evaluations, int32_t *round_trips, void *ws,
+                           size_t ws_bytes, void *stream) {
     const vecchia_cov cov{VECCHIA_MATERN, VECCHIA_EUCLIDEAN, nu};
     return vecchia_mle_cov(locs, z, nbr, n, m, &cov, theta0, options, theta, loglik, grad, iterations, evaluations,
-                           ws, ws_bytes, stream);
+                           round_trips, ws, ws_bytes, stream);
 }

@@ -120,3 +120,42 @@ def test_mle_power_exponential_great_circle_matches_oracle_fit(v):
     assert abs(res["loglik"] - ll_at) <= 1e-10 * abs(ll_at)
     assert res["loglik"] >= ll_ref - 1e-9 * abs(ll_ref)
     np.testing.assert_allclose(res["theta"], th_ref, rtol=2e-3)
+
+
+def test_batched_line_search_takes_the_same_steps_in_fewer_round_trips(v):
+    """Trial step lengths evaluated as theta columns of one batched launch: the line search accepts the
+    step one-at-a-time backtracking accepts (batched evaluations are bitwise equal to single ones), so
+    the fit is bitwise the same, in fewer device round trips."""
+    import time
+
+    import torch
+    rng = np.random.default_rng(630)
+    n, m, nu = 3000, 30, 1.5
+    locs = wl.uniform_locations(rng, n)[rng.permutation(n)]
+    z = wl.exact_gp_draw(rng, locs, nu, 1.2, 0.1, 0.03)
+    nbr = wl.nearest_previous_neighbours(locs, m)
+    dev = torch.device("cuda:0")
+    args = (torch.from_numpy(locs).to(dev), torch.from_numpy(z).to(dev), torch.from_numpy(nbr).to(dev), m, nu)
+    theta0 = (0.3, 0.5, 0.3)  # far from the truth: the early steps back off
+    fits = {}
+    for k in (1, 4, 8):
+        opt = v.mle_default_options()
+        opt.trial_steps = k
+        t0 = time.perf_counter()
+        fits[k] = v.vecchia_mle(*args, theta0, options=opt)
+        fits[k]["seconds"] = time.perf_counter() - t0
+        print("trial_steps", k, fits[k], flush=True)
+    for k in (4, 8):
+        assert np.array_equal(fits[k]["theta"], fits[1]["theta"]), k
+        assert fits[k]["loglik"] == fits[1]["loglik"]
+        assert fits[k]["iterations"] == fits[1]["iterations"]
+        assert fits[k]["round_trips"] <= fits[1]["round_trips"]
+        assert fits[k]["evaluations"] >= fits[1]["evaluations"]
+    assert fits[1]["round_trips"] == fits[1]["evaluations"]
+    # the start is poor enough that some line searches back off, which batching saves trips on
+    assert fits[1]["evaluations"] > fits[1]["iterations"] + 1
+    assert fits[4]["round_trips"] < fits[1]["round_trips"]
+    opt = v.mle_default_options()
+    opt.trial_steps = 9
+    with pytest.raises(v.VecchiaError):
+        v.vecchia_mle(*args, theta0, options=opt)
