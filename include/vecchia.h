@@ -107,6 +107,23 @@ int vecchia_loglik_grad(const double *locs, const double *z, const int32_t *nbr,
                         size_t ws_bytes, void *stream);
 
 /*
+ * vecchia_loglik_grad without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments and results as vecchia_loglik_grad
+ * minus ws / ws_bytes, bitwise equal to it with the same kernel variant.  The
+ * per-point rows live in a static device array of the library (about 10.6 MB
+ * on every GPU it runs on, held until the process ends), which every call on
+ * that GPU shares: calls that overlap on one GPU race and give wrong results.
+ * Points are evaluated in slices of 2^18 through that array.
+ *   n at most VECCHIA_NOALLOC_MAX_N; larger n returns VECCHIA_EUNSUPPORTED.
+ * Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED or VECCHIA_EHIP.
+ */
+#define VECCHIA_NOALLOC_MAX_N (1 << 26)
+int vecchia_loglik_grad_noalloc(const double *locs, const double *z, const int32_t *nbr, int64_t n, int32_t m,
+                                double nu, const double *theta, double *out, double *grad, int64_t *status,
+                                void *stream);
+
+/*
  * Per-point terms, for checking individual conditionals.
  *   idx    [dev] int64[nidx] points to evaluate, each in [0, n); NULL = all
  *          points (then nidx must equal n)

@@ -89,6 +89,8 @@ def _load():
         lib.vecchia_loglik.argtypes = [P, P, P, I64, I32, D, P, P, P, P, SZ, P]
         lib.vecchia_loglik_grad.restype = ctypes.c_int
         lib.vecchia_loglik_grad.argtypes = [P, P, P, I64, I32, D, P, P, P, P, P, SZ, P]
+        lib.vecchia_loglik_grad_noalloc.restype = ctypes.c_int
+        lib.vecchia_loglik_grad_noalloc.argtypes = [P, P, P, I64, I32, D, P, P, P, P, P]
         lib.vecchia_loglik_terms.restype = ctypes.c_int
         lib.vecchia_loglik_terms.argtypes = [P, P, P, I64, I32, D, P, P, I64, P, P, P, P]
         lib.vecchia_variant_feasible.restype = ctypes.c_int
@@ -322,6 +324,22 @@ def vecchia_loglik_grad(locs, z, nbr, m: int, nu: float, theta, out=None, grad=N
                                      _ptr(theta), _ptr(out), _ptr(grad), _ptr(status), _ptr(ws), _nbytes(ws),
                                      _stream(stream))
     _check(rc, "vecchia_loglik_grad")
+    return out, grad, status
+
+
+VECCHIA_NOALLOC_MAX_N = 1 << 26
+
+
+def vecchia_loglik_grad_noalloc(locs, z, nbr, m: int, nu: float, theta, out, grad, status, stream=None):
+    """vecchia_loglik_grad without a workspace (the library's static scratch): for callers that cannot
+    allocate, so the outputs are required; calls that overlap on one GPU race."""
+    n = _as_inputs(locs, z, nbr, m)
+    dev = z.device
+    _theta_check(theta, dev)
+    _outputs_check(dev, out=out, grad=grad, status=status)
+    rc = _load().vecchia_loglik_grad_noalloc(_ptr(locs), _ptr(z), _ptr(nbr) if m > 0 else None, n, m, float(nu),
+                                             _ptr(theta), _ptr(out), _ptr(grad), _ptr(status), _stream(stream))
+    _check(rc, "vecchia_loglik_grad_noalloc")
     return out, grad, status
 
 
