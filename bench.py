@@ -327,15 +327,28 @@ def multitheta_times(v, stream):
                                   ws=ws, stream=stream)
 
     p_ms, p_min = event_ms(stream, plain, steps=3, warmup=1)
-    plan = v.BatchedPlan([(L, Z, N, f.m)], P, f.nu, True)
-    b_out, b_grad, b_st = plan.outputs()
-    graph = plan.capture(thetas, b_out, b_grad, b_st)
-    b_ms, b_min = event_ms(stream, lambda: graph.launch(stream), steps=3, warmup=1)
-    torch.cuda.synchronize()
-    ok = bool((sts == 0).all()) and bool((b_st == 0).all())
-    same = bool(torch.equal(b_out.reshape(-1), outs.reshape(-1))) and bool(torch.equal(b_grad.reshape(-1, 3), grads))
-    graph.close()
-    plan.close()
+
+    def batched(lockstep):
+        prev = v.set_lockstep(lockstep)
+        try:
+            plan = v.BatchedPlan([(L, Z, N, f.m)], P, f.nu, True)
+        finally:
+            v.set_lockstep(prev)
+        b_out, b_grad, b_st = plan.outputs()
+        graph = plan.capture(thetas, b_out, b_grad, b_st)
+        b_ms, _ = event_ms(stream, lambda: graph.launch(stream), steps=3, warmup=1)
+        torch.cuda.synchronize()
+        ok = bool((b_st == 0).all())
+        same = bool(torch.equal(b_out.reshape(-1), outs.reshape(-1))) and bool(torch.equal(b_grad.reshape(-1, 3),
+                                                                                          grads))
+        groups = plan.groups()
+        graph.close()
+        plan.close()
+        return b_ms, ok, same, groups
+
+    b_ms, b_ok, b_same, groups = batched(True)
+    s_ms, s_ok, s_same, _ = batched(False)
+    ok = bool((sts == 0).all()) and b_ok and s_ok
     flops, _, _ = workload_counts(f.n, f.m, True)
     conds = P * f.n
     return {"workload": f"{w.name} value+gradient", "n": f.n, "m": f.m, "nu": f.nu, "thetas": P,
@@ -343,7 +356,9 @@ def multitheta_times(v, stream):
             "batched_cond_per_s": conds / (b_ms * 1e-3), "batched_speedup": p_ms / b_ms,
             "batched_frac": P * flops / (b_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
             "plain_frac": P * flops / (p_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-            "status_ok": ok, "batched_equals_plain_bitwise": same}
+            "vectors_per_workgroup": groups,
+            "batched_one_vector_per_workgroup_ms": s_ms,
+            "status_ok": ok, "batched_equals_plain_bitwise": b_same and s_same}
 
 
 def m_sweep_times(v, stream, n: int = 250_000, ms=(10, 30, 60, 90, 120, 150), nu: float = 1.5):

@@ -293,6 +293,19 @@ int vecchia_plan_num_classes(const vecchia_plan *plan);
 int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_rows, int32_t *variant,
                             int32_t *nfields, int64_t *items);
 
+/* Parameter vectors one workgroup of class c evaluates together: G > 1 when the
+ * class's variant has a lockstep form (one wavefront per vector with four
+ * vectors, two wavefronts per vector with two, up to 94 neighbours) and
+ * ntheta is a multiple of G, else 1.  The G vectors of a point share the
+ * gathered neighbours and the diagonal-tile factorisations; each vector's
+ * result is bitwise the single-vector one.  -VECCHIA_EINVAL for a bad plan or
+ * class. */
+int vecchia_plan_class_group(const vecchia_plan *plan, int32_t c);
+
+/* Whether plans created from now on may use lockstep forms (default 1);
+ * returns the previous setting.  Process-wide; for comparisons. */
+int vecchia_set_lockstep(int32_t enable);
+
 /* Releases the plan (host memory).  Not while a graph captured from it is used. */
 int vecchia_plan_destroy(vecchia_plan *plan);
 

@@ -115,6 +115,10 @@ def _load():
         lib.vecchia_plan_class_info.restype = ctypes.c_int
         lib.vecchia_plan_class_info.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                                 ctypes.POINTER(I32), ctypes.POINTER(I64)]
+        lib.vecchia_plan_class_group.restype = ctypes.c_int
+        lib.vecchia_plan_class_group.argtypes = [P, I32]
+        lib.vecchia_set_lockstep.restype = ctypes.c_int
+        lib.vecchia_set_lockstep.argtypes = [I32]
         lib.vecchia_plan_destroy.restype = ctypes.c_int
         lib.vecchia_plan_destroy.argtypes = [P]
         lib.vecchia_plan_loglik.restype = ctypes.c_int
@@ -573,6 +577,17 @@ class BatchedPlan:
             out.append((T.value, var.value, nfc.value, items.value))
         return out
 
+    def groups(self):
+        """Parameter vectors per workgroup (lockstep group size) of each tile class."""
+        lib = _load()
+        out = []
+        for c in range(lib.vecchia_plan_num_classes(self.handle)):
+            g = lib.vecchia_plan_class_group(self.handle, c)
+            if g < 0:
+                _check(-g, "vecchia_plan_class_group")
+            out.append(g)
+        return out
+
     def _check_arrays(self, thetas, out, grad, status):
         ne = self.nf * self.ntheta
         _theta_check(thetas, self.device, ne)
@@ -683,6 +698,12 @@ class BatchedGraph:
             self.close()
         except Exception:
             pass
+
+
+def set_lockstep(enable: bool) -> bool:
+    """Whether plans created from now on may evaluate several parameter vectors per workgroup (default on);
+    returns the previous setting (process-wide)."""
+    return bool(_load().vecchia_set_lockstep(int(bool(enable))))
 
 
 def vecchia_autotune(locs, z, nbr, m: int, nu: float, theta, with_grad: bool, sample: int = 20000, reps: int = 3,

@@ -6,7 +6,10 @@
 // T = ceil((m+2)/16).  Items of a class are (field, theta, point) triples;
 // one launch per class evaluates all of them with the class's variant, one
 // workgroup per item, last points first (their conditioning sets are the
-// full ones), so the short sets of the first points fill the tail.  The
+// full ones), so the short sets of the first points fill the tail.  Where the
+// variant has a lockstep form and ntheta is a multiple of its group size G,
+// one workgroup takes G consecutive items instead: one point, G parameter
+// vectors (same arithmetic per vector, so the same bits).  The
 // classes run one after the other on the caller's stream.  A segmented reduction then forms every evaluation (field, theta)
 // with the same fixed-order sum as the single-evaluation entry points, so a
 // batched result is bitwise equal to the single call with the same variant.
@@ -19,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <vector>
 
@@ -31,6 +35,8 @@ using namespace vecchia;
 namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+std::atomic<bool> g_lockstep{true};  // plans use lockstep forms where they exist
 
 constexpr int kPutWords = 256;  // 8-byte words of table one writing launch carries (2 KB of kernel arguments)
 
@@ -50,6 +56,7 @@ __global__ void __launch_bounds__(kPutWords) put_words_kernel(uint64_t *__restri
 struct ClassPlan {
     int T = 0;
     int variant = 0;
+    int group = 1;               // parameter vectors per workgroup (lockstep form when > 1)
     int32_t m_max = 0;
     std::vector<int32_t> fidx;   // fields of the class, larger m first
     std::vector<int64_t> item0;  // prefix sums of ntheta * n over fidx (size nfc + 1)
@@ -159,6 +166,7 @@ int run_batched(const vecchia_plan *p, const double *thetas, double *out, double
         a.t_begin = 0;
         a.t_end = C.item0.back();
         a.m_max = C.m_max;
+        a.group = C.group;
         const int rc = launch_any(p->nuc, p->grad, C.variant, a, s);
         if (rc != VECCHIA_OK) return rc;
     }
@@ -241,6 +249,11 @@ int plan_build(const vecchia_field *fields, int32_t nf, int32_t ntheta, const ve
             C.m_max = std::max(C.m_max, fields[f].m);
         }
         C.variant = resolve_variant(C.m_max, p->grad, 0);
+        // several parameter vectors of a point share one workgroup when the
+        // shape has a lockstep form and the vectors divide into its groups
+        const int W = variant_waves(C.variant);
+        const int G = W > 0 ? lockstep_group(T, W) : 1;
+        if (g_lockstep.load() && G > 1 && ntheta % G == 0) C.group = G;
         p->classes.push_back(C);
     }
     // device table: the field array, then per class its field list and item offsets
@@ -301,6 +314,13 @@ int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_r
     if (items) *items = C.item0.back();
     return VECCHIA_OK;
 }
+
+int vecchia_plan_class_group(const vecchia_plan *plan, int32_t c) {
+    if (!plan || c < 0 || c >= (int32_t)plan->classes.size()) return -VECCHIA_EINVAL;
+    return plan->classes[c].group;
+}
+
+int vecchia_set_lockstep(int32_t enable) { return g_lockstep.exchange(enable != 0) ? 1 : 0; }
 
 int vecchia_plan_destroy(vecchia_plan *plan) {
     if (!plan) return VECCHIA_EINVAL;

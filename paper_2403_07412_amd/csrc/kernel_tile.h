@@ -64,33 +64,53 @@ __host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_co
 // while column t is processed, slot R > t holds the panel tile X_R (T-layout,
 // lane-major), and slot t' <= t holds factor t' in the CUR format, copied
 // there once every reader of X_t' has passed a barrier.
-template <int T, int W, bool GRAD, bool GCD = false>
+//
+// A workgroup that evaluates G parameter vectors of one conditional in
+// lockstep keeps G copies of everything that depends on the parameters (CUR,
+// SLOT, YP, Q, UB, SCAL, RED); the gathered coordinates, observations and the
+// exponential table are shared.  G = 1 is the one-vector layout.  With one
+// wavefront per vector (INPLACE) there is no CUR: each vector's wavefront
+// stores diagonal tile t + 1 into slot t + 1 once its trailing updates have
+// read X_(t+1) there, and the tile is factored in place.
+template <int T, int W, bool GRAD, bool GCD = false, int G = 1>
 struct TileLds {
     static constexpr int KP = 16 * T;
     static constexpr int DS = 288;                        // a 16 x 17 tile, then 16 inverse pivots
+    static constexpr bool INPLACE = G > 1 && W == 1;
     static constexpr int NPAR = (W > 1 && T > 1) ? 2 : 1;
-    static constexpr int CUR = 0;                         // [NPAR][DS]  diagonal tile / its factor
-    static constexpr int SLOT = CUR + NPAR * DS;          // [T][DS]     panel tiles / stored factors
-    static constexpr int XY = SLOT + T * DS;              // [KP][2]     coordinates
-    static constexpr int ZV = XY + 2 * KP;                // [KP]        observations
-    static constexpr int YP = ZV + KP;                    // [KP]        factor row k+1
-    static constexpr int Q = YP + KP;                     // [KP][2]     back-substitution right-hand sides (gradient)
-    static constexpr int UB = Q + (GRAD ? 2 * KP : 0);    // [KP][2]     solutions (u, b) (gradient)
-    static constexpr int SCAL = UB + (GRAD ? 2 * KP : 0); // [16]        scalars: [0] L_kk
-    static constexpr int RED = SCAL + 16;                 // [2][32]     reductions (two values, up to 8 waves x 4 rows)
-    static constexpr int EXPT = RED + 64;                 // [64][2]     2^(j/64) as hi, lo for exp_neg_tab
-    static constexpr int CL = EXPT + 2 * kExpTableSize;   // [KP]        cos(latitude) (great-circle codes only)
+    static constexpr int CUR = 0;                         // [G][NPAR][DS]  diagonal tile / its factor
+    static constexpr int SLOT = CUR + (INPLACE ? 0 : G * NPAR * DS);  // [G][T][DS] panel tiles / factors
+    static constexpr int XY = SLOT + G * T * DS;          // [KP][2]        coordinates
+    static constexpr int ZV = XY + 2 * KP;                // [KP]           observations
+    static constexpr int YP = ZV + KP;                    // [G][KP]        factor row k+1
+    static constexpr int Q = YP + G * KP;                 // [G][KP][2]     back-substitution right-hand sides (gradient)
+    static constexpr int UB = Q + (GRAD ? G * 2 * KP : 0);    // [G][KP][2] solutions (u, b) (gradient)
+    static constexpr int SCAL = UB + (GRAD ? G * 2 * KP : 0); // [G][16]    scalars: [0] L_kk
+    static constexpr int RED = SCAL + G * 16;             // [G][2][32]     reductions (two values, up to 8 waves x 4 rows)
+    static constexpr int EXPT = RED + G * 64;             // [64][2]        2^(j/64) as hi, lo for exp_neg_tab
+    static constexpr int CL = EXPT + 2 * kExpTableSize;   // [KP]           cos(latitude) (great-circle codes only)
     static constexpr int TOTAL = CL + (GCD ? KP : 0);
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
+    // per-parameter-vector strides
+    static constexpr int CUR_G = NPAR * DS, SLOT_G = T * DS, YP_G = KP, QUB_G = 2 * KP, SCAL_G = 16, RED_G = 64;
 };
 
-// TileLds<T, W, grad, gcd>::TOTAL, for the occupancy estimate.
-__host__ __device__ constexpr int tile_lds_doubles(int T, int W, bool grad, bool gcd) {
-    return ((W > 1 && T > 1) ? 2 : 1) * 288 + T * 288 + 16 * T * (4 + (grad ? 4 : 0) + (gcd ? 1 : 0)) + 16 + 64 +
-           2 * kExpTableSize;
+// TileLds<T, W, grad, gcd, G>::TOTAL, for the occupancy estimate.
+__host__ __device__ constexpr int tile_lds_doubles(int T, int W, bool grad, bool gcd, int G = 1) {
+    return (G > 1 && W == 1 ? 0 : G * ((W > 1 && T > 1) ? 2 : 1) * 288) + G * T * 288 +
+           16 * T * (3 + G * (1 + (grad ? 4 : 0)) + (gcd ? 1 : 0)) + G * (16 + 64) + 2 * kExpTableSize;
 }
 static_assert(TileLds<8, 4, true, false>::TOTAL == tile_lds_doubles(8, 4, true, false), "LDS estimate out of date");
 static_assert(TileLds<3, 1, false, true>::TOTAL == tile_lds_doubles(3, 1, false, true), "LDS estimate out of date");
+static_assert(TileLds<4, 1, true, true, 4>::TOTAL == tile_lds_doubles(4, 1, true, true, 4), "LDS estimate out of date");
+static_assert(TileLds<5, 2, false, false, 2>::TOTAL == tile_lds_doubles(5, 2, false, false, 2), "LDS estimate out of date");
+
+// Parameter vectors a workgroup evaluates in lockstep, per shape: four with
+// one wavefront per vector, two with two; larger workgroups and more tile
+// rows keep one vector (G = 1).  Only these group sizes are compiled.
+__host__ __device__ constexpr int lockstep_group(int T, int W) {
+    return T > 6 ? 1 : W == 1 ? 4 : W == 2 ? 2 : 1;
+}
 
 // Shapes measured faster with one more workgroup per CU than the register
 // estimate below allows, at the price of a small spill: T = 8, W = 4 (m from
@@ -105,16 +125,18 @@ __host__ __device__ constexpr bool tile_measured_raise(int T, int W, bool gcd) {
 // VGPRs per tile (16 when the beta-derivative tiles are kept) plus about 72
 // for the diagonal factorisation, the covariance code and addressing (the
 // compiler reports 143 VGPRs for T = 8, W = 4 with the gradient, nine tiles).
-__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool grad, bool gcd = false) {
-    const int lds = tile_lds_doubles(T, W, grad, gcd) * 8;
+// A lockstep workgroup (G parameter vectors) has G W wavefronts.
+__host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d, bool grad, bool gcd = false,
+                                                      int G = 1) {
+    const int lds = tile_lds_doubles(T, W, grad, gcd, G) * 8;
     const int blocks_lds = 163840 / lds;
     const int need = 8 * tiles_per_wave(T, W) * (keep_d ? 2 : 1) + 72 + (gcd ? 16 : 0);
     const int wps_regs = 512 / need;                 // wavefronts per SIMD the registers allow
-    const int blocks_regs = (wps_regs * 4) / W;      // workgroups per CU the registers allow
+    const int blocks_regs = (wps_regs * 4) / (W * G);  // workgroups per CU the registers allow
     int blocks = blocks_lds < blocks_regs ? blocks_lds : blocks_regs;
     if (blocks < 1) blocks = 1;
-    if (!keep_d && tile_measured_raise(T, W, gcd) && blocks + 1 <= blocks_lds) blocks += 1;
-    int wps = (blocks * W + 3) / 4;
+    if (G == 1 && !keep_d && tile_measured_raise(T, W, gcd) && blocks + 1 <= blocks_lds) blocks += 1;
+    int wps = (blocks * W * G + 3) / 4;
     if (wps < 1) wps = 1;
     if (wps > 8) wps = 8;
     return wps;
@@ -129,10 +151,10 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d,
 // kept whenever two wavefronts per SIMD still fit (measured: the 250,000-point
 // great-circle power-exponential gradient took 11.7 ms keeping them at two
 // wavefronts per SIMD, 17.0 ms recomputing at three).
-__host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
+__host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false, int G = 1) {
     return VECCHIA_KEEP_DBETA &&
-           (tile_waves_per_simd(T, W, true, true, gcd) >= tile_waves_per_simd(T, W, false, true, gcd) ||
-            (gcd && tile_waves_per_simd(T, W, true, true, gcd) >= 2));
+           (tile_waves_per_simd(T, W, true, true, gcd, G) >= tile_waves_per_simd(T, W, false, true, gcd, G) ||
+            (gcd && tile_waves_per_simd(T, W, true, true, gcd, G) >= 2));
 }
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -236,11 +258,13 @@ __device__ __forceinline__ double row_sum16(double v) {
     return v;
 }
 
-// Workgroup sums of two values in a fixed order (rows, then rows of waves in
-// ascending order); every thread gets both totals.  `red` holds 2 * 4W doubles.
+// Sums of two values over the W wavefronts of a parameter vector's group in a
+// fixed order (rows, then rows of waves in ascending order); every thread of
+// the group gets both totals.  `red` holds 2 * 4W doubles per group.  Every
+// wavefront of the workgroup calls it together.
 template <int W>
 __device__ __forceinline__ void block_sum2(double &a, double &b, double *red) {
-    const int l = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int l = threadIdx.x % kWave, w = (threadIdx.x / kWave) % W;
     a = row_sum16(a);
     b = row_sum16(b);
     __syncthreads();
@@ -304,7 +328,12 @@ __device__ __forceinline__ void store_panel_tlayout(const dvec4 &v, double *slot
 // k reaches rows up to k.  A pivot that is not positive and finite turns
 // L_kk, and with it the conditional's value, into NaN, which the caller
 // reports.
-template <int T>
+//
+// NG is the number of different tiles the wave factors at once (1, 2 or 4,
+// one per parameter vector of a lockstep workgroup): row group g works on tile
+// g % NG, with D, scal and yp pointing to that tile's buffers, and the 4 / NG
+// row groups that hold the same tile share its writes.
+template <int T, int NG = 1>
 __device__ __forceinline__ void factor_diag(int t, int k, double *D, double *scal, double *yp) {
     int l = threadIdx.x % kWave;
     asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
@@ -343,19 +372,23 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *D, double *sca
     });
     // L_kk = 1 / (its refined reciprocal square-root pivot), within an ulp of
     // pivot * rsqrt(pivot)
-    if (g == 0 && j == jk) scal[0] = 1.0 / myinv;
-    if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
+    static_assert(NG == 1 || NG == 2 || NG == 4, "one, two or four tiles per wave");
+    constexpr int NC = 4 / NG;  // row groups holding the same tile
+    const int gc = g / NG;      // this group's share among them
+    const bool lead = gc == 0;
+    if (lead && j == jk) scal[0] = 1.0 / myinv;
+    if (lead && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
             if (c < jy) yp[base + c] = R[c];
     }
-    // publish: the four row groups hold the same rows and write a quarter of
-    // the columns each
+    // publish: the row groups holding the same rows write 1 / NC of the
+    // columns each
 #pragma unroll
     for (int c = 0; c < 16; ++c)
-        if (c % 4 == g) D[j * 17 + c] = (c < j) ? R[c] : 0.0;
-    if (g == 0) D[j * 17 + 16] = myinv;
-    if (g == 1) D[272 + j] = myinv;
+        if (c % NC == gc) D[j * 17 + c] = (c < j) ? R[c] : 0.0;
+    if (lead) D[j * 17 + 16] = myinv;
+    if (gc == (NC > 1 ? 1 : 0)) D[272 + j] = myinv;
     __builtin_amdgcn_s_setprio(0);
 }
 
@@ -420,19 +453,38 @@ __device__ __forceinline__ void panel_solve(dvec4 (&x)[P], const double *D) {
 
 // One conditional (modes as lds_conditional: qloc == NULL for the
 // likelihood term of point i, else the prediction at qloc from row i of nbr).
-template <int T, int W, int KC, bool GRAD>
+//
+// With G > 1 the workgroup evaluates the conditional of point i for G
+// parameter vectors at once (likelihood mode only): wavefronts [qW, qW + W)
+// form the group of vector q, each wavefront passes its group's parameters in
+// P and receives its group's result.  The groups share the gather and the
+// barriers; one wavefront factors the G diagonal tiles of a column together
+// (one per row group), and one wavefront per two vectors runs the back
+// substitution's diagonal solves.  Every vector's arithmetic is the one the
+// single-vector form performs, in the same order, so the results are bitwise
+// the same.
+template <int T, int W, int KC, bool GRAD, int G = 1>
 __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ locs, const double *__restrict__ z,
                                     const int32_t *__restrict__ nbr, int64_t i, int64_t n, int32_t m,
                                     const double *qloc, const Params &P, double *smem) {
+    static_assert(G == 1 || G == 2 || G == 4, "one, two or four parameter vectors per workgroup");
     constexpr bool GCD = kc_gcd(KC);
-    using Ls = TileLds<T, W, GRAD, GCD>;
-    constexpr int NT = W * kWave;
+    using Ls = TileLds<T, W, GRAD, GCD, G>;
+    constexpr int NT = G * W * kWave;
+    constexpr int NTG = W * kWave;  // threads per parameter vector
     constexpr int NTW = tiles_per_wave(T, W);
     constexpr int NTILES = tile_count(T);
     constexpr int KP = Ls::KP;
     constexpr int DS = Ls::DS;
     const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int wg = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int w = G > 1 ? wg % W : wg;   // wavefront within the vector's group
+    const int wq = G > 1 ? wg / W : 0;   // the group's parameter vector
+    const int tg = tid % NTG;            // thread within the group
+    double *const CURq = smem + Ls::CUR + wq * Ls::CUR_G;
+    double *const SLOTq = smem + Ls::SLOT + wq * Ls::SLOT_G;
+    double *const YPq = smem + Ls::YP + wq * Ls::YP_G;
+    double *const SCALq = smem + Ls::SCAL + wq * Ls::SCAL_G;
     const int l = tid % kWave;
     const int g = l / 16, j = l % 16;
     const int64_t lim = qloc ? n : i;
@@ -526,7 +578,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
             for (int r = 0; r < 4; ++r) tile[s][r] = augment_value(16 * R_ + 4 * r + g, b, k, tile[s][r], Z);
         }
-        if (R_ == 0 && C_ == 0) store_rowmajor17(tile[s], smem + Ls::CUR);
+        if (R_ == 0 && C_ == 0) store_rowmajor17(tile[s], Ls::INPLACE ? SLOTq : CURq);
     }
 
     // blocked right-looking Cholesky
@@ -537,16 +589,28 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // loop, which at this register budget spill to scratch
         int lo = l * 4;
         asm volatile("" : "+v"(lo));
-        double *D = smem + Ls::CUR + (Ls::NPAR == 2 ? (t & 1) : 0) * DS;
+        const int par = Ls::INPLACE ? t * DS : (Ls::NPAR == 2 ? (t & 1) : 0) * DS;
+        double *D = (Ls::INPLACE ? SLOTq : CURq) + par;
         const bool diag_owner = w == tile_index(T, t, t) % W;
         // 1. diagonal tile t (fully updated, stored to D by its owner)
-        if (diag_owner) factor_diag<T>(t, k, D, smem + Ls::SCAL, smem + Ls::YP);
+        if constexpr (G == 1) {
+            if (diag_owner) factor_diag<T>(t, k, D, SCALq, YPq);
+        } else {
+            // every group's tile t is in place; the owner in group 0 factors
+            // all G of them, row group g the tile of vector g % G
+            __syncthreads();
+            if (diag_owner && wq == 0) {
+                const int gq = g % G;
+                double *Dg = Ls::INPLACE ? smem + Ls::SLOT + gq * Ls::SLOT_G : smem + Ls::CUR + gq * Ls::CUR_G;
+                factor_diag<T, G>(t, k, Dg + par, smem + Ls::SCAL + gq * Ls::SCAL_G, smem + Ls::YP + gq * Ls::YP_G);
+            }
+        }
         __syncthreads();
         // the factor goes to slot t for the back substitution: the panel tile
         // X_t it replaces was last read by the trailing update of column t - 1
-        if constexpr (GRAD) {
+        if constexpr (GRAD && !Ls::INPLACE) {
             if (diag_owner) {
-                double *St = smem + Ls::SLOT + t * DS;
+                double *St = SLOTq + t * DS;
                 for (int e = l; e < DS; e += kWave) St[e] = D[e];
             }
         }
@@ -558,27 +622,33 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                 dvec4 one[1] = {tile[s]};
                 panel_solve<1>(one, D);
                 tile[s] = one[0];
-                store_panel_tlayout(tile[s], smem + Ls::SLOT + SR(s) * DS);
+                store_panel_tlayout(tile[s], SLOTq + SR(s) * DS);
             }
         }
         __syncthreads();
         // 3. trailing update of the tiles right of column t, the next diagonal
         // tile first: it is then handed to the factorisation
-        double *Dn = smem + Ls::CUR + (Ls::NPAR == 2 ? ((t + 1) & 1) : 0) * DS;
+        double *Dn = CURq + (Ls::NPAR == 2 ? ((t + 1) & 1) : 0) * DS;
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
             for (int s = 0; s < NTW; ++s) {
                 const bool nextdiag = SR(s) == t + 1 && SC(s) == t + 1;
                 if (SC(s) > t && (pass == 0) == nextdiag) {
-                    const dvec4 xr = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SR(s) * DS + lo);
-                    const dvec4 xc = *reinterpret_cast<const dvec4 *>(smem + Ls::SLOT + SC(s) * DS + lo);
+                    const dvec4 xr = *reinterpret_cast<const dvec4 *>(SLOTq + SR(s) * DS + lo);
+                    const dvec4 xc = *reinterpret_cast<const dvec4 *>(SLOTq + SC(s) * DS + lo);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         tile[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xr[q], xc[q], tile[s], 0, 0, 0);
-                    if (nextdiag) store_rowmajor17(tile[s], Dn);
+                    if (nextdiag && !Ls::INPLACE) store_rowmajor17(tile[s], Dn);
                 }
             }
+        }
+        if constexpr (Ls::INPLACE) {
+            // X_(t+1) in slot t + 1 has had its last reader (this wavefront)
+#pragma unroll
+            for (int s = 0; s < NTW; ++s)
+                if (SR(s) == t + 1 && SC(s) == t + 1) store_rowmajor17(tile[s], SLOTq + (t + 1) * DS);
         }
     }
     // observation row k+1 from the tiles left of its diagonal tile: row jy of
@@ -589,14 +659,14 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         if (SR(s) == ty && SC(s) < ty) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (4 * r + g == jy) smem[Ls::YP + 16 * SC(s) + j] = tile[s][r];
+                if (4 * r + g == jy) YPq[16 * SC(s) + j] = tile[s][r];
         }
     }
     __syncthreads();
 
     CondOut o;
-    const double Lkk = smem[Ls::SCAL + 0];
-    const double wv = smem[Ls::YP + k];
+    const double Lkk = SCALq[0];
+    const double wv = YPq[k];
     o.ell = -0.5 * (kLog2Pi + 2.0 * log(Lkk) + wv * wv);
     o.g0 = o.g1 = o.g2 = 0.0;
     o.var = Lkk * Lkk;
@@ -614,18 +684,28 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // subtract L_tC^T x_t from q_C on the matrix cores: an N-layout tile
         // as the first operand enters as its transpose, and x_t as the second
         // operand sits in lanes (g, j < 2), register q holding x_j[4q + g].
-        double *Q = smem + Ls::Q, *UB = smem + Ls::UB;
-        const double *YP = smem + Ls::YP;
-        for (int t = tid; t < KP; t += NT) {
+        //
+        // In a lockstep workgroup the diagonal owner of the even group q solves
+        // for vectors q and q + 1: row groups 2 and 3 take the right-hand sides
+        // of vector q + 1.
+        double *Q = smem + Ls::Q + wq * Ls::QUB_G, *UB = smem + Ls::UB + wq * Ls::QUB_G;
+        const double *YP = YPq;
+        for (int t = tg; t < KP; t += NTG) {
             Q[2 * t] = (t < k) ? rr * YP[t] : (t == k ? half * Lkk : 0.0);
             Q[2 * t + 1] = (t == k) ? Lkk : 0.0;
         }
         __syncthreads();
+        // the vector this lane's row group serves in the diagonal solves, and its offset
+        const int sq = G > 1 ? wq + g / 2 : 0;
+        const int sg = G > 1 ? g % 2 : g;
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
-            const double *St = smem + Ls::SLOT + t * DS;  // strictly lower L_tt, 1 / L_jj in column 16
-            if (w == tile_index(T, t, t) % W) {
-                double qv = (g < 2) ? Q[2 * (16 * t + j) + g] : 0.0;
+            // strictly lower L_tt, 1 / L_jj in column 16, of the vector this lane serves
+            const double *St = smem + Ls::SLOT + sq * Ls::SLOT_G + t * DS;
+            if (w == tile_index(T, t, t) % W && (G == 1 || wq % 2 == 0)) {
+                double *Qs = smem + Ls::Q + sq * Ls::QUB_G;
+                double *UBs = smem + Ls::UB + sq * Ls::QUB_G;
+                double qv = (G > 1 || g < 2) ? Qs[2 * (16 * t + j) + sg] : 0.0;
                 // column c from the last: x_c = q_c / L_cc, then q_n -= L_cn x_c (n < c);
                 // weights -L[c][n] / L[c][c] (zero for n >= c), four steps loaded ahead
                 double la[4], da[4], wg[4];
@@ -637,24 +717,24 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
 #pragma unroll
                 for (int q = 0; q < 4; ++q) wg[q] = -(la[q] * da[q]);
                 static_for<0, 4>([&](auto gc) {
-                    constexpr int G = decltype(gc)::value;
-                    if constexpr (G < 3) {
+                    constexpr int S = decltype(gc)::value;  // steps 4S .. 4S + 3 from the last column
+                    if constexpr (S < 3) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            la[q] = St[(11 - 4 * G - q) * 17 + j];
-                            da[q] = St[272 + 11 - 4 * G - q];
+                            la[q] = St[(11 - 4 * S - q) * 17 + j];
+                            da[q] = St[272 + 11 - 4 * S - q];
                         }
                     }
                     static_for<0, 4>([&](auto qc) {
                         constexpr int q = decltype(qc)::value;
-                        fma_bcast_row_self<15 - 4 * G - q, true>(qv, wg[q]);
+                        fma_bcast_row_self<15 - 4 * S - q, true>(qv, wg[q]);
                     });
-                    if constexpr (G < 3) {
+                    if constexpr (S < 3) {
 #pragma unroll
                         for (int q = 0; q < 4; ++q) wg[q] = -(la[q] * da[q]);
                     }
                 });
-                if (g < 2) UB[2 * (16 * t + j) + g] = qv * St[272 + j];
+                if (G > 1 || g < 2) UBs[2 * (16 * t + j) + sg] = qv * St[272 + j];
             }
             __syncthreads();
             if (t > 0) {
@@ -686,7 +766,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // one half, and D_aa (zero in exact arithmetic, about 2^-500 sigma2 /
         // beta^2 after sqrt_pos) is set to zero.
         double ub = 0.0;
-        for (int t = tid; t <= k; t += NT) ub += UB[2 * t] * UB[2 * t + 1];
+        for (int t = tg; t <= k; t += NTG) ub += UB[2 * t] * UB[2 * t + 1];
         double gb = 0.0;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
@@ -723,7 +803,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
             }
             gb = fma(wt, acc, gb);
         }
-        block_sum2<W>(ub, gb, smem + Ls::RED);
+        block_sum2<W>(ub, gb, smem + Ls::RED + wq * Ls::RED_G);
         o.g2 = ub;
         o.g0 = (0.5 * (rr * rr * c - 1.0) - P.tau2 * ub) / P.sigma2;
         o.g1 = gb;

@@ -32,17 +32,20 @@ struct LdsImpl {
     }
 };
 
-template <int T, int W, int KC, bool GRAD>
+// G > 1: G parameter vectors of one conditional per workgroup (lockstep).
+template <int T, int W, int KC, bool GRAD, int G = 1>
 struct TileImpl {
-    static constexpr int NT = W * kWave;
+    static constexpr int NT = G * W * kWave;
+    static constexpr int GROUP = G;
+    static constexpr int WAVES = W;  // wavefronts per parameter vector
     static constexpr bool GCD = kc_gcd(KC);
     static constexpr int WPE = VECCHIA_WPE_OVERRIDE > 0
                                    ? VECCHIA_WPE_OVERRIDE
-                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD), GRAD, GCD);
-    static size_t smem(int) { return TileLds<T, W, GRAD, GCD>::BYTES; }
+                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD, G), GRAD, GCD, G);
+    static size_t smem(int) { return TileLds<T, W, GRAD, GCD, G>::BYTES; }
     static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int64_t n,
                                   int32_t m, const double *qloc, const Params &P, double *sm) {
-        return tile_conditional<T, W, KC, GRAD>(locs, z, nbr, i, n, m, qloc, P, sm);
+        return tile_conditional<T, W, KC, GRAD, G>(locs, z, nbr, i, n, m, qloc, P, sm);
     }
 };
 
@@ -174,12 +177,69 @@ hipError_t allow_smem(K kernel, size_t bytes) {
     return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Batched mode, lockstep form: the G wavefront groups of a workgroup take the
+// G consecutive items t, t + 1, .., t + G - 1 (t a multiple of G), which are
+// the same point of one field for G consecutive parameter vectors because
+// ntheta is a multiple of G.  Each group loads its own parameters; a group
+// whose vector is invalid runs on placeholder parameters (the workgroup's
+// barriers need every group) and reports its row as failed.
+template <class Impl>
+__device__ __forceinline__ void cond_item_group(const KernelArgs &a, int64_t t0, double *smem) {
+    constexpr int G = Impl::GROUP;
+    const int wq = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) / Impl::WAVES;
+    const int64_t t = t0 + wq;
+    int lo = 0, hi = a.nfc;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.item0[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const FieldDev &F = a.fields[a.fidx[lo]];
+    const int64_t r = t - a.item0[lo];
+    const int64_t ip = r / a.ntheta;
+    const int64_t q = r - ip * a.ntheta;
+    const int64_t n = F.n, i = n - 1 - ip;
+    const int64_t row = F.vals0 + q * n + i;
+    Params P = load_params(a.theta + 3 * (F.eval0 + q), a.alpha);
+    const bool valid = P.valid;
+    if (!valid) {
+        P.sigma2 = 1.0;
+        P.beta = 1.0;
+        P.inv_beta = 1.0;
+        P.tau2 = 1.0;
+    }
+    static_assert(G > 1, "the lockstep form");
+    CondOut o = Impl::run(F.locs, F.z, F.nbr, i, n, (int32_t)F.m, nullptr, P, smem);
+    const bool bad = o.bad || !valid;
+    if (bad) o.ell = o.g0 = o.g1 = o.g2 = __builtin_nan("");
+    if (threadIdx.x % (Impl::WAVES * kWave) == 0) {
+        a.ell[row * a.ell_stride] = o.ell;
+        if (a.g) {
+            a.g[row * a.g_stride + 0] = o.g0;
+            a.g[row * a.g_stride + 1] = o.g1;
+            a.g[row * a.g_stride + 2] = o.g2;
+        }
+        if (a.flags) a.flags[row] = bad ? 1 : 0;
+        if (a.status && bad && valid) atomicMin(a.status, (unsigned long long)(t + 1));
+    }
+}
+
+template <class Impl>
+__global__ void __launch_bounds__(Impl::NT) __attribute__((amdgpu_waves_per_eu(Impl::WPE)))
+    cond_group_kernel(const KernelArgs a) {
+    extern __shared__ double smem[];
+    cond_item_group<Impl>(a, a.t0 + (int64_t)Impl::GROUP * blockIdx.x, smem);
+}
+
 // A launch request: kernel arguments plus the item range [t_begin, t_end)
 // and the largest m among the items (sizes the LDS of the unblocked kernel).
+// group > 1 asks for the lockstep form with that many parameter vectors per
+// workgroup (batched mode; the range and ntheta are multiples of it).
 struct EvalArgs {
     KernelArgs k;
     int64_t t_begin, t_end;
     int32_t m_max;
+    int32_t group;
 };
 
 template <class Impl>
@@ -198,6 +258,25 @@ int launch_cond_impl(const EvalArgs &a, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
 }
 
+template <class Impl>
+int launch_group_impl(const EvalArgs &a, hipStream_t s) {
+    constexpr int G = Impl::GROUP;
+    if (a.t_end <= a.t_begin) return VECCHIA_OK;
+    if (!a.k.fields || a.k.qlocs || a.k.ntheta % G != 0 || a.t_begin % G != 0 || a.t_end % G != 0)
+        return VECCHIA_EINVAL;
+    const size_t smem = Impl::smem(a.m_max);
+    auto kern = cond_group_kernel<Impl>;
+    if (allow_smem(kern, smem) != hipSuccess) return VECCHIA_EHIP;
+    constexpr int64_t kMaxGrid = (int64_t)1 << 22;
+    for (int64_t t0 = a.t_begin; t0 < a.t_end; t0 += kMaxGrid * G) {
+        const int64_t grid = std::min<int64_t>((a.t_end - t0) / G, kMaxGrid);
+        KernelArgs k = a.k;
+        k.t0 = t0;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(Impl::NT), smem, s, k);
+    }
+    return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
+}
+
 // Kernel variants.  The tiled family is instantiated for T = ceil((m+2)/16)
 // tile rows and W wavefronts per conditional.
 enum Variant { V_AUTO = 0, V_UNBLOCKED = 1, V_TILE_W1 = 2, V_TILE_W2 = 3, V_TILE_W4 = 4, V_TILE_W8 = 5 };
@@ -205,6 +284,17 @@ enum Variant { V_AUTO = 0, V_UNBLOCKED = 1, V_TILE_W1 = 2, V_TILE_W2 = 3, V_TILE
 constexpr int kMaxT = (VECCHIA_MAX_M + 2 + 15) / 16;
 
 inline int tile_rows(int m) { return (m + 2 + 15) / 16; }
+
+// wavefronts per conditional of a tiled variant (0 for the unblocked kernel)
+inline int variant_waves(int variant) {
+    switch (variant) {
+        case V_TILE_W1: return 1;
+        case V_TILE_W2: return 2;
+        case V_TILE_W4: return 4;
+        case V_TILE_W8: return 8;
+        default: return 0;
+    }
+}
 
 // register budget: at most 20 tiles per wavefront
 inline bool variant_feasible(int variant, int m) {
@@ -237,6 +327,13 @@ int launch_tile(const EvalArgs &a, hipStream_t s) {
     } else if constexpr (tiles_per_wave(T, W) > 20) {
         return VECCHIA_EUNSUPPORTED;
     } else {
+        constexpr int G = lockstep_group(T, W);
+        if (a.group > 1) {
+            if constexpr (G > 1) {
+                if (a.group == G) return launch_group_impl<TileImpl<T, W, KC, GRAD, G>>(a, s);
+            }
+            return VECCHIA_EUNSUPPORTED;
+        }
         return launch_cond_impl<TileImpl<T, W, KC, GRAD>>(a, s);
     }
 }
@@ -269,6 +366,7 @@ int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
     const int T = tile_rows(a.m_max);
     switch (variant) {
         case V_UNBLOCKED:
+            if (a.group > 1) return VECCHIA_EUNSUPPORTED;
             return launch_cond_impl<LdsImpl<KC, GRAD>>(a, s);
         case V_TILE_W1: return launch_tile_w<KC, GRAD, 1>(T, a, s);
         case V_TILE_W2: return launch_tile_w<KC, GRAD, 2>(T, a, s);

@@ -115,6 +115,42 @@ def test_batched_workspace_query_and_plan_are_host_only(lib):
         assert lib.vecchia_plan_destroy(handle) == 0
 
 
+def _expected_group(T, variant, ntheta):
+    """Lockstep group size of a class: four vectors with one wavefront each, two with two, up to six tile rows."""
+    waves = {2: 1, 3: 2, 4: 4, 5: 8}.get(variant, 0)
+    G = 1 if T > 6 else {1: 4, 2: 2}.get(waves, 1)
+    return G if G > 1 and ntheta % G == 0 else 1
+
+
+@pytest.mark.parametrize("ntheta", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("with_grad", [0, 1])
+def test_plan_picks_lockstep_groups_on_the_host(lib, ntheta, with_grad):
+    import paper_2403_07412_amd as v
+    specs = [(1000, 10), (1000, 30), (1000, 45), (1000, 60), (1000, 75), (1000, 94), (1000, 95), (1000, 120)]
+    arr = _fake_fields(v, specs)
+    T, var = ctypes.c_int32(), ctypes.c_int32()
+    for enable in (1, 0):
+        prev = lib.vecchia_set_lockstep(enable)
+        handle = ctypes.c_void_p()
+        try:
+            assert lib.vecchia_plan_create(arr, len(specs), ntheta, ctypes.c_double(1.5), with_grad,
+                                           ctypes.byref(handle)) == 0
+        finally:
+            lib.vecchia_set_lockstep(prev)
+        try:
+            groups = []
+            for c in range(lib.vecchia_plan_num_classes(handle)):
+                assert lib.vecchia_plan_class_info(handle, c, ctypes.byref(T), ctypes.byref(var), None, None) == 0
+                g = lib.vecchia_plan_class_group(handle, c)
+                assert g == (_expected_group(T.value, var.value, ntheta) if enable else 1), (T.value, var.value)
+                groups.append(g)
+            if enable and ntheta % 4 == 0:
+                assert max(groups) == 4
+            assert lib.vecchia_plan_class_group(handle, len(groups)) < 0
+        finally:
+            assert lib.vecchia_plan_destroy(handle) == 0
+
+
 def test_batched_rejects_oversized_batches_on_the_host(lib):
     import paper_2403_07412_amd as v
     arr = _fake_fields(v, [(10, 5), (10, 5)])

@@ -77,6 +77,52 @@ def test_batched_equals_single_calls_bitwise_and_oracle(v, with_grad):
     plan.close()
 
 
+LOCKSTEP_SPECS = [(700, 10), (1500, 30), (900, 62), (1, 5), (0, 20), (610, 94), (400, 120), (64, 3), (17, 40),
+                  (350, 75)]
+
+
+@pytest.mark.parametrize("ntheta", [2, 4, 8])
+@pytest.mark.parametrize("with_grad", [True, False])
+def test_lockstep_groups_equal_one_vector_workgroups_bitwise(v, with_grad, ntheta):
+    """Several parameter vectors per workgroup (shared gather, shared diagonal factorisations) give the bits of
+    one vector per workgroup, for every class shape, with an invalid vector inside a group."""
+    import torch
+    rng = np.random.default_rng(81 + ntheta)
+    nu = 2.5
+    fields = make_fields(rng, LOCKSTEP_SPECS, nu)
+    th = random_thetas(rng, len(LOCKSTEP_SPECS), ntheta)
+    th[2, 1] = [-1.0, 0.1, 0.0]
+    thetas = torch.from_numpy(th).cuda()
+    prev = v.set_lockstep(True)
+    try:
+        plan = v.BatchedPlan([f[1] for f in fields], ntheta, nu, with_grad)
+        v.set_lockstep(False)
+        plan1 = v.BatchedPlan([f[1] for f in fields], ntheta, nu, with_grad)
+    finally:
+        v.set_lockstep(prev)
+    groups = plan.groups()
+    print("classes", plan.classes(), "groups", groups, flush=True)
+    assert max(groups) > 1 and all(g == 1 for g in plan1.groups())
+    out, grad, status = plan(thetas)
+    out1, grad1, status1 = plan1(thetas)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[2, 1] == -1
+    st[2, 1] = 0
+    assert (st == 0).all()
+    assert torch.equal(status, status1)
+    assert torch.equal(out.view(torch.int64), out1.view(torch.int64))
+    if with_grad:
+        assert torch.equal(grad.view(torch.int64), grad1.view(torch.int64))
+    # and the oracle, on one vector of a lockstep class
+    fi, q = 2, 0
+    f = fields[fi][0]
+    ell, gt = oracle.terms(f.locs, f.z, f.nbr, f.m, nu, th[fi, q], with_grad=True)
+    assert_total_close(out[fi, q].item(), oracle.compensated_sum(ell), 1e-10, "lockstep field 2")
+    plan.close()
+    plan1.close()
+
+
 def test_graph_replays_match_eager(v):
     import torch
     rng = np.random.default_rng(78)
