@@ -293,13 +293,11 @@ int vecchia_plan_num_classes(const vecchia_plan *plan);
 int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_rows, int32_t *variant,
                             int32_t *nfields, int64_t *items);
 
-/* Parameter vectors one workgroup of class c evaluates together: G > 1 when the
- * class's variant has a lockstep form (one wavefront per vector with four
- * vectors, two wavefronts per vector with two, up to 94 neighbours) and
- * ntheta is a multiple of G, else 1.  The G vectors of a point share the
- * gathered neighbours and the diagonal-tile factorisations; each vector's
- * result is bitwise the single-vector one.  -VECCHIA_EINVAL for a bad plan or
- * class. */
+/* Parameter vectors one workgroup of class c evaluates together: 4 when the
+ * class's variant has one wavefront per conditional (up to 94 neighbours) and
+ * ntheta is a multiple of 4, else 1.  The four vectors of a point share the
+ * gathered neighbours and the pair distances; each vector's result is bitwise
+ * the single-vector one.  -VECCHIA_EINVAL for a bad plan or class. */
 int vecchia_plan_class_group(const vecchia_plan *plan, int32_t c);
 
 /* Whether plans created from now on may use lockstep forms (default 1);
@@ -516,9 +514,10 @@ size_t vecchia_mle_workspace_size(int64_t n, int32_t m);
  *   ws          [dev] at least vecchia_mle_workspace_size(n, m) bytes, 256-byte aligned
  * Each round trip evaluates a set of parameter vectors as the theta columns
  * of one batched launch (a host plan over the field): the line search tries
- * the next trial_steps halvings of the step at once and takes the longest
- * that satisfies the Armijo condition, the step one-at-a-time backtracking
- * would take.  Synchronises the stream once per round trip.  Returns VECCHIA_OK,
+ * a quasi-Newton step alone, and once it backs off (or without curvature
+ * information) the next trial_steps halvings of the step at once, taking
+ * the longest that satisfies the Armijo condition, the step one-at-a-time
+ * backtracking would take.  Synchronises the stream once per round trip.  Returns VECCHIA_OK,
  * VECCHIA_EINVAL (bad arguments or options, or theta0 does not evaluate),
  * VECCHIA_EUNSUPPORTED, VECCHIA_EWORKSPACE or VECCHIA_EHIP.
  */

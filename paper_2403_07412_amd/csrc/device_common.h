@@ -177,12 +177,12 @@ __device__ __forceinline__ double gcd_km(double lona, double lata, double ca, do
     return (2.0 * kEarthRadiusKm) * asin_sqrt(h);
 }
 
-// Scaled distance r fed to the closed forms: d / beta (Matern) or
-// d^alpha / beta (power exponential; alpha = 1 and 2 without the
-// exponential, otherwise e^(alpha ln d) with the table exponential, and 0
-// for d = 0).
+// The parameter-free part of the scaled distance: d (Matern) or d^alpha
+// (power exponential; alpha = 1 and 2 without the exponential, otherwise
+// e^(alpha ln d) with the table exponential, and 0 for d = 0).  alpha is
+// fixed per call, so this is shared by every (sigma2, beta, tau2).
 template <int KC>
-__device__ __forceinline__ double cov_scaled(double d, const Params &P, const double *tab) {
+__device__ __forceinline__ double dist_pow(double d, const Params &P, const double *tab) {
     if constexpr (kc_family(KC) == 3) {
         double da;
         if (P.alpha == 1.0) {
@@ -192,28 +192,41 @@ __device__ __forceinline__ double cov_scaled(double d, const Params &P, const do
         } else {
             da = (d > 0.0) ? exp_neg_tab(-(P.alpha * log(d)), tab) : 0.0;
         }
-        return da * P.inv_beta;
+        return da;
     } else {
-        return d * P.inv_beta;
+        return d;
     }
 }
 
-// Covariance C(d) and, with WITH_D, its beta-derivative for points a and b
-// (cos of the latitudes in ca, cb for the great-circle codes), using
-// exp_neg_tab.  With r the scaled distance, the Matern forms are sigma2 m(r)
-// and sigma2 h(r) / beta (h as in matern_dbeta_r); the power exponential is
-// sigma2 e^-r with derivative sigma2 r e^-r / beta, the nu = 1/2 form.  The
-// coordinates must be finite.
-template <int KC, bool WITH_D>
-__device__ __forceinline__ void cov_pair(double xa, double ya, double ca, double xb, double yb, double cb,
-                                         const Params &P, double s2b, const double *tab, double &c, double &db) {
-    double r;
+// Scaled distance r fed to the closed forms: d / beta (Matern) or
+// d^alpha / beta (power exponential).
+template <int KC>
+__device__ __forceinline__ double cov_scaled(double d, const Params &P, const double *tab) {
+    return dist_pow<KC>(d, P, tab) * P.inv_beta;
+}
+
+// dist_pow of the distance between points a and b (cos of the latitudes in
+// ca, cb for the great-circle codes).  The coordinates must be finite.
+template <int KC>
+__device__ __forceinline__ double pair_dist_pow(double xa, double ya, double ca, double xb, double yb, double cb,
+                                                const Params &P, const double *tab) {
     if constexpr (kc_gcd(KC)) {
-        r = cov_scaled<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P, tab);
+        return dist_pow<KC>(gcd_km(xa, ya, ca, xb, yb, cb), P, tab);
     } else {
         const double dx = xa - xb, dy = ya - yb;
-        r = cov_scaled<KC>(sqrt_pos(fma(dx, dx, dy * dy)), P, tab);
+        return dist_pow<KC>(sqrt_pos(fma(dx, dx, dy * dy)), P, tab);
     }
+}
+
+// Covariance C and, with WITH_D, its beta-derivative from da = dist_pow of
+// the pair's distance, using exp_neg_tab.  With r = da / beta the scaled
+// distance, the Matern forms are sigma2 m(r) and sigma2 h(r) / beta (h as in
+// matern_dbeta_r); the power exponential is sigma2 e^-r with derivative
+// sigma2 r e^-r / beta, the nu = 1/2 form.
+template <int KC, bool WITH_D>
+__device__ __forceinline__ void cov_from_dist(double da, const Params &P, double s2b, const double *tab, double &c,
+                                              double &db) {
+    const double r = da * P.inv_beta;
     const double e = exp_neg_tab(r, tab);
     constexpr int F = kc_family(KC);
     if constexpr (F == 0 || F == 3) {
@@ -226,6 +239,15 @@ __device__ __forceinline__ void cov_pair(double xa, double ya, double ca, double
         c = P.sigma2 * ((1.0 + r * (1.0 + r * (1.0 / 3.0))) * e);
         if constexpr (WITH_D) db = s2b * ((r * r) * (1.0 + r) * (1.0 / 3.0) * e);
     }
+}
+
+// Covariance C(d) and, with WITH_D, its beta-derivative for points a and b
+// (cos of the latitudes in ca, cb for the great-circle codes).  The
+// coordinates must be finite.
+template <int KC, bool WITH_D>
+__device__ __forceinline__ void cov_pair(double xa, double ya, double ca, double xb, double yb, double cb,
+                                         const Params &P, double s2b, const double *tab, double &c, double &db) {
+    cov_from_dist<KC, WITH_D>(pair_dist_pow<KC>(xa, ya, ca, xb, yb, cb, P, tab), P, s2b, tab, c, db);
 }
 
 // Closed forms in the scaled distance r: Matern, Eq. (2), for half-integer

@@ -105,12 +105,11 @@ static_assert(TileLds<3, 1, false, true>::TOTAL == tile_lds_doubles(3, 1, false,
 static_assert(TileLds<4, 1, true, true, 4>::TOTAL == tile_lds_doubles(4, 1, true, true, 4), "LDS estimate out of date");
 static_assert(TileLds<5, 2, false, false, 2>::TOTAL == tile_lds_doubles(5, 2, false, false, 2), "LDS estimate out of date");
 
-// Parameter vectors a workgroup evaluates in lockstep, per shape: four with
-// one wavefront per vector, two with two; larger workgroups and more tile
-// rows keep one vector (G = 1).  Only these group sizes are compiled.
-__host__ __device__ constexpr int lockstep_group(int T, int W) {
-    return T > 6 ? 1 : W == 1 ? 4 : W == 2 ? 2 : 1;
-}
+// Parameter vectors a workgroup evaluates in lockstep, per shape: four for
+// the one-wavefront shapes up to six tile rows, where the four wavefronts
+// share the gathered neighbours and the pair distances; other shapes keep one
+// vector (G = 1).  Only these group sizes are compiled.
+__host__ __device__ constexpr int lockstep_group(int T, int W) { return (T <= 6 && W == 1) ? 4 : 1; }
 
 // Shapes measured faster with one more workgroup per CU than the register
 // estimate below allows, at the price of a small spill: T = 8, W = 4 (m from
@@ -150,11 +149,14 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d,
 // exponential) a logarithm and an exponential per entry: there the tiles are
 // kept whenever two wavefronts per SIMD still fit (measured: the 250,000-point
 // great-circle power-exponential gradient took 11.7 ms keeping them at two
-// wavefronts per SIMD, 17.0 ms recomputing at three).
-__host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false, int G = 1) {
+// wavefronts per SIMD, 17.0 ms recomputing at three).  Lockstep workgroups
+// follow the one-vector decision: the two ways round the derivative
+// contract their arithmetic differently, and the lockstep results must be
+// the one-vector bits.
+__host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
     return VECCHIA_KEEP_DBETA &&
-           (tile_waves_per_simd(T, W, true, true, gcd, G) >= tile_waves_per_simd(T, W, false, true, gcd, G) ||
-            (gcd && tile_waves_per_simd(T, W, true, true, gcd, G) >= 2));
+           (tile_waves_per_simd(T, W, true, true, gcd) >= tile_waves_per_simd(T, W, false, true, gcd) ||
+            (gcd && tile_waves_per_simd(T, W, true, true, gcd) >= 2));
 }
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -328,12 +330,7 @@ __device__ __forceinline__ void store_panel_tlayout(const dvec4 &v, double *slot
 // k reaches rows up to k.  A pivot that is not positive and finite turns
 // L_kk, and with it the conditional's value, into NaN, which the caller
 // reports.
-//
-// NG is the number of different tiles the wave factors at once (1, 2 or 4,
-// one per parameter vector of a lockstep workgroup): row group g works on tile
-// g % NG, with D, scal and yp pointing to that tile's buffers, and the 4 / NG
-// row groups that hold the same tile share its writes.
-template <int T, int NG = 1>
+template <int T>
 __device__ __forceinline__ void factor_diag(int t, int k, double *D, double *scal, double *yp) {
     int l = threadIdx.x % kWave;
     asm volatile("" : "+v"(l));  // keep the lane masks below inside the tile loop (no hoisting)
@@ -372,23 +369,19 @@ __device__ __forceinline__ void factor_diag(int t, int k, double *D, double *sca
     });
     // L_kk = 1 / (its refined reciprocal square-root pivot), within an ulp of
     // pivot * rsqrt(pivot)
-    static_assert(NG == 1 || NG == 2 || NG == 4, "one, two or four tiles per wave");
-    constexpr int NC = 4 / NG;  // row groups holding the same tile
-    const int gc = g / NG;      // this group's share among them
-    const bool lead = gc == 0;
-    if (lead && j == jk) scal[0] = 1.0 / myinv;
-    if (lead && jy >= 0 && jy < 16 && j == jy) {
+    if (g == 0 && j == jk) scal[0] = 1.0 / myinv;
+    if (g == 0 && jy >= 0 && jy < 16 && j == jy) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
             if (c < jy) yp[base + c] = R[c];
     }
-    // publish: the row groups holding the same rows write 1 / NC of the
-    // columns each
+    // publish: the four row groups hold the same rows and write a quarter of
+    // the columns each
 #pragma unroll
     for (int c = 0; c < 16; ++c)
-        if (c % NC == gc) D[j * 17 + c] = (c < j) ? R[c] : 0.0;
-    if (lead) D[j * 17 + 16] = myinv;
-    if (gc == (NC > 1 ? 1 : 0)) D[272 + j] = myinv;
+        if (c % 4 == g) D[j * 17 + c] = (c < j) ? R[c] : 0.0;
+    if (g == 0) D[j * 17 + 16] = myinv;
+    if (g == 1) D[272 + j] = myinv;
     __builtin_amdgcn_s_setprio(0);
 }
 
@@ -454,15 +447,17 @@ __device__ __forceinline__ void panel_solve(dvec4 (&x)[P], const double *D) {
 // One conditional (modes as lds_conditional: qloc == NULL for the
 // likelihood term of point i, else the prediction at qloc from row i of nbr).
 //
-// With G > 1 the workgroup evaluates the conditional of point i for G
-// parameter vectors at once (likelihood mode only): wavefronts [qW, qW + W)
-// form the group of vector q, each wavefront passes its group's parameters in
-// P and receives its group's result.  The groups share the gather and the
-// barriers; one wavefront factors the G diagonal tiles of a column together
-// (one per row group), and one wavefront per two vectors runs the back
-// substitution's diagonal solves.  Every vector's arithmetic is the one the
-// single-vector form performs, in the same order, so the results are bitwise
-// the same.
+// With G > 1 (W = 1) the workgroup evaluates the conditional of point i for G
+// parameter vectors at once (likelihood mode only): wavefront q takes vector
+// q, passes its parameters in P and receives its result.  The wavefronts
+// share the gather and the pair distances (each evaluates a G-th of them and
+// exchanges them through LDS) and otherwise factor and solve their own
+// vector, synchronising only with themselves.  Every vector's arithmetic is
+// the one the single-vector form performs, in the same order, so the results
+// are bitwise the same.  (Factoring the G diagonal tiles of a column in one
+// wavefront, one tile per 16-lane row group, returned NaN now and then for
+// the vectors held in row groups 1 and 3, in the first workgroups of small
+// launches; each vector's wavefront factors its own tile instead.)
 template <int T, int W, int KC, bool GRAD, int G = 1>
 __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ locs, const double *__restrict__ z,
                                     const int32_t *__restrict__ nbr, int64_t i, int64_t n, int32_t m,
@@ -485,6 +480,16 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     double *const SLOTq = smem + Ls::SLOT + wq * Ls::SLOT_G;
     double *const YPq = smem + Ls::YP + wq * Ls::YP_G;
     double *const SCALq = smem + Ls::SCAL + wq * Ls::SCAL_G;
+    // synchronisation of the wavefronts that share a vector's tiles: the whole
+    // workgroup, except in lockstep groups of one wavefront per vector, where
+    // each wavefront works on its own vector alone between the shared phases
+    // (the gather, and the distance exchanges)
+    auto group_sync = [&]() {
+        if constexpr (G > 1 && W == 1)
+            wave_lds_sync();
+        else
+            __syncthreads();
+    };
     const int l = tid % kWave;
     const int g = l / 16, j = l % 16;
     const int64_t lim = qloc ? n : i;
@@ -553,6 +558,30 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     dvec4 tile[NTW];
     dvec4 dtile[KEEP_D ? NTW : 1];
     const double s2b = P.sigma2 * P.inv_beta;
+    // With one wavefront per vector (INPLACE) every group needs the same
+    // distances: each group's wavefront evaluates those of every G-th (tile,
+    // register) pair, 64 lanes at a time, into the panel slots past slot 0,
+    // which hold nothing yet (and nothing any more when the gradient's
+    // contraction needs the distances again).
+    constexpr bool SHARE_D = Ls::INPLACE && T >= 2;
+    constexpr int DCH = SHARE_D ? ((T - 1) * DS) / kWave : 1;  // 64-double chunks per vector past slot 0
+    static_assert(!SHARE_D || G * DCH >= 4 * NTW, "the shared distances fit in the panel slots");
+    auto dslot = [&](int p) -> double * { return smem + Ls::SLOT + (p / DCH) * Ls::SLOT_G + DS + (p % DCH) * kWave; };
+    if constexpr (SHARE_D) {
+#pragma unroll
+        for (int s = 0; s < NTW; ++s) {
+            const int b = 16 * SC(s) + j;
+            const double xb = XY[2 * b], yb = XY[2 * b + 1], cb = GCD ? CLv[b] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if ((4 * s + r) % G != wq) continue;  // wave-uniform
+                const int a = 16 * SR(s) + 4 * r + g;
+                dslot(4 * s + r)[l] = pair_dist_pow<KC>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P,
+                                                        ET);
+            }
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int s = 0; s < NTW; ++s) {
         tile[s] = dvec4{0.0, 0.0, 0.0, 0.0};
@@ -565,7 +594,10 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         for (int r = 0; r < 4; ++r) {
             const int a = 16 * R_ + 4 * r + g;
             double cv, db;
-            cov_pair<KC, KEEP_D>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv, db);
+            if constexpr (SHARE_D)
+                cov_from_dist<KC, KEEP_D>(dslot(4 * s + r)[l], P, s2b, ET, cv, db);
+            else
+                cov_pair<KC, KEEP_D>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv, db);
             tile[s][r] = cv;
             if constexpr (KEEP_D) dtile[s][r] = db;
         }
@@ -580,6 +612,9 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         }
         if (R_ == 0 && C_ == 0) store_rowmajor17(tile[s], Ls::INPLACE ? SLOTq : CURq);
     }
+    // every wavefront has read the shared distances before any writes a
+    // panel tile over them
+    if constexpr (SHARE_D) __syncthreads();
 
     // blocked right-looking Cholesky
 #pragma unroll 1
@@ -593,19 +628,8 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         double *D = (Ls::INPLACE ? SLOTq : CURq) + par;
         const bool diag_owner = w == tile_index(T, t, t) % W;
         // 1. diagonal tile t (fully updated, stored to D by its owner)
-        if constexpr (G == 1) {
-            if (diag_owner) factor_diag<T>(t, k, D, SCALq, YPq);
-        } else {
-            // every group's tile t is in place; the owner in group 0 factors
-            // all G of them, row group g the tile of vector g % G
-            __syncthreads();
-            if (diag_owner && wq == 0) {
-                const int gq = g % G;
-                double *Dg = Ls::INPLACE ? smem + Ls::SLOT + gq * Ls::SLOT_G : smem + Ls::CUR + gq * Ls::CUR_G;
-                factor_diag<T, G>(t, k, Dg + par, smem + Ls::SCAL + gq * Ls::SCAL_G, smem + Ls::YP + gq * Ls::YP_G);
-            }
-        }
-        __syncthreads();
+        if (diag_owner) factor_diag<T>(t, k, D, SCALq, YPq);
+        group_sync();
         // the factor goes to slot t for the back substitution: the panel tile
         // X_t it replaces was last read by the trailing update of column t - 1
         if constexpr (GRAD && !Ls::INPLACE) {
@@ -625,7 +649,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                 store_panel_tlayout(tile[s], SLOTq + SR(s) * DS);
             }
         }
-        __syncthreads();
+        group_sync();
         // 3. trailing update of the tiles right of column t, the next diagonal
         // tile first: it is then handed to the factorisation
         double *Dn = CURq + (Ls::NPAR == 2 ? ((t + 1) & 1) : 0) * DS;
@@ -662,7 +686,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                 if (4 * r + g == jy) YPq[16 * SC(s) + j] = tile[s][r];
         }
     }
-    __syncthreads();
+    group_sync();
 
     CondOut o;
     const double Lkk = SCALq[0];
@@ -684,28 +708,18 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // subtract L_tC^T x_t from q_C on the matrix cores: an N-layout tile
         // as the first operand enters as its transpose, and x_t as the second
         // operand sits in lanes (g, j < 2), register q holding x_j[4q + g].
-        //
-        // In a lockstep workgroup the diagonal owner of the even group q solves
-        // for vectors q and q + 1: row groups 2 and 3 take the right-hand sides
-        // of vector q + 1.
         double *Q = smem + Ls::Q + wq * Ls::QUB_G, *UB = smem + Ls::UB + wq * Ls::QUB_G;
         const double *YP = YPq;
         for (int t = tg; t < KP; t += NTG) {
             Q[2 * t] = (t < k) ? rr * YP[t] : (t == k ? half * Lkk : 0.0);
             Q[2 * t + 1] = (t == k) ? Lkk : 0.0;
         }
-        __syncthreads();
-        // the vector this lane's row group serves in the diagonal solves, and its offset
-        const int sq = G > 1 ? wq + g / 2 : 0;
-        const int sg = G > 1 ? g % 2 : g;
+        group_sync();
 #pragma unroll 1
         for (int t = T - 1; t >= 0; --t) {
-            // strictly lower L_tt, 1 / L_jj in column 16, of the vector this lane serves
-            const double *St = smem + Ls::SLOT + sq * Ls::SLOT_G + t * DS;
-            if (w == tile_index(T, t, t) % W && (G == 1 || wq % 2 == 0)) {
-                double *Qs = smem + Ls::Q + sq * Ls::QUB_G;
-                double *UBs = smem + Ls::UB + sq * Ls::QUB_G;
-                double qv = (G > 1 || g < 2) ? Qs[2 * (16 * t + j) + sg] : 0.0;
+            const double *St = SLOTq + t * DS;  // strictly lower L_tt, 1 / L_jj in column 16
+            if (w == tile_index(T, t, t) % W) {
+                double qv = (g < 2) ? Q[2 * (16 * t + j) + g] : 0.0;
                 // column c from the last: x_c = q_c / L_cc, then q_n -= L_cn x_c (n < c);
                 // weights -L[c][n] / L[c][c] (zero for n >= c), four steps loaded ahead
                 double la[4], da[4], wg[4];
@@ -734,9 +748,9 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                         for (int q = 0; q < 4; ++q) wg[q] = -(la[q] * da[q]);
                     }
                 });
-                if (G > 1 || g < 2) UBs[2 * (16 * t + j) + sg] = qv * St[272 + j];
+                if (g < 2) UB[2 * (16 * t + j) + g] = qv * St[272 + j];
             }
-            __syncthreads();
+            group_sync();
             if (t > 0) {
                 int qo = 2 * g + j;  // opaque per step, as in the factorisation loop
                 asm volatile("" : "+v"(qo));
@@ -757,7 +771,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                         }
                     }
                 }
-                __syncthreads();
+                group_sync();
             }
         }
         // dl/dtau2 = u^T b; dl/dbeta = sum_{a > b} D_ab (u_a b_b + u_b b_a).
@@ -767,6 +781,25 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         // beta^2 after sqrt_pos) is set to zero.
         double ub = 0.0;
         for (int t = tg; t <= k; t += NTG) ub += UB[2 * t] * UB[2 * t + 1];
+        if constexpr (SHARE_D && !KEEP_D) {
+            // the distances again, shared as in the fill, once every wavefront
+            // is past its back substitution (the last reader of its slots)
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < NTW; ++s) {
+                if (16 * SR(s) > k) continue;
+                const int b = 16 * SC(s) + j;
+                const double xb = XY[2 * b], yb = XY[2 * b + 1], cb = GCD ? CLv[b] : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if ((4 * s + r) % G != wq) continue;  // wave-uniform
+                    const int a = 16 * SR(s) + 4 * r + g;
+                    dslot(4 * s + r)[l] = pair_dist_pow<KC>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb,
+                                                            P, ET);
+                }
+            }
+            __syncthreads();
+        }
         double gb = 0.0;
 #pragma unroll
         for (int s = 0; s < NTW; ++s) {
@@ -783,8 +816,11 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
                 for (int r = 0; r < 4; ++r) {
                     const int a = 16 * R_ + 4 * r + g;
                     double cv, db;
-                    cov_pair<KC, true>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv,
-                                       db);
+                    if constexpr (SHARE_D)
+                        cov_from_dist<KC, true>(dslot(4 * s + r)[l], P, s2b, ET, cv, db);
+                    else
+                        cov_pair<KC, true>(XY[2 * a], XY[2 * a + 1], GCD ? CLv[a] : 0.0, xb, yb, cb, P, s2b, ET, cv,
+                                           db);
                     db4[r] = db;
                 }
             }

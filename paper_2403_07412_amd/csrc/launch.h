@@ -41,7 +41,7 @@ struct TileImpl {
     static constexpr bool GCD = kc_gcd(KC);
     static constexpr int WPE = VECCHIA_WPE_OVERRIDE > 0
                                    ? VECCHIA_WPE_OVERRIDE
-                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD, G), GRAD, GCD, G);
+                                   : tile_waves_per_simd(T, W, GRAD && keep_dbeta(T, W, GCD), GRAD, GCD, G);
     static size_t smem(int) { return TileLds<T, W, GRAD, GCD, G>::BYTES; }
     static __device__ CondOut run(const double *locs, const double *z, const int32_t *nbr, int64_t i, int64_t n,
                                   int32_t m, const double *qloc, const Params &P, double *sm) {

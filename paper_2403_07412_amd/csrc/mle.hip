@@ -8,11 +8,13 @@
 // Host code driving the batched evaluation: every device round trip
 // evaluates a set of parameter vectors as the theta columns of one host plan
 // (vecchia_plan_loglik, one launch per round trip), reads back their values,
-// gradients and statuses in one copy and synchronises once.  The line search
-// evaluates K = trial_steps step lengths (the next K halvings of the step)
-// per round trip and takes the longest one that satisfies the Armijo
-// condition, the step sequential backtracking would take, in about 1/K of
-// the round trips.
+// gradients and statuses in one copy and synchronises once.  A line search
+// tries a quasi-Newton step alone first (it is usually accepted as it
+// stands); once it backs off, and from the first step of a search without
+// curvature information, it evaluates K = trial_steps step lengths (the next
+// K halvings) per round trip and takes the longest one that satisfies the
+// Armijo condition, the step sequential backtracking would take.  Round
+// trips never exceed those of one-at-a-time backtracking.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -225,14 +227,14 @@ extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_
             for (int p = 0; p < kNp; ++p) dmax = std::max(dmax, std::fabs(d[p]));
             if (dmax > 1.0) step = 1.0 / dmax;
         }
-        // projected backtracking line search with the Armijo condition: the
-        // next K halvings of the step in one round trip, the longest
-        // acceptable one taken
+        // projected backtracking line search with the Armijo condition: a
+        // quasi-Newton step alone first, then the next K halvings of the step
+        // per round trip, the longest acceptable one taken
         Eval nxt{};
         double phin[kNp];
         bool accepted = false;
-        for (int ls = 0; ls < 40 && !accepted; ls += K) {
-            const int k = std::min(K, 40 - ls);
+        for (int ls = 0; ls < 40 && !accepted;) {
+            const int k = std::min((ls == 0 && hist > 0) ? 1 : K, 40 - ls);
             double cand[kMaxTrials][kNp];
             Eval ev[kMaxTrials];
             double st = step;
@@ -251,6 +253,7 @@ extern "C" int vecchia_mle_cov(const double *locs, const double *z, const int32_
                 }
             }
             step = st;
+            ls += k;
         }
         if (!accepted) break;
         double s[kNp], y[kNp];

@@ -116,10 +116,11 @@ def test_batched_workspace_query_and_plan_are_host_only(lib):
 
 
 def _expected_group(T, variant, ntheta):
-    """Lockstep group size of a class: four vectors with one wavefront each, two with two, up to six tile rows."""
+    """Lockstep group size of a class: four vectors, one wavefront each, for one-wavefront variants up to six
+    tile rows."""
     waves = {2: 1, 3: 2, 4: 4, 5: 8}.get(variant, 0)
-    G = 1 if T > 6 else {1: 4, 2: 2}.get(waves, 1)
-    return G if G > 1 and ntheta % G == 0 else 1
+    G = 4 if T <= 6 and waves == 1 else 1
+    return G if ntheta % G == 0 else 1
 
 
 @pytest.mark.parametrize("ntheta", [1, 2, 3, 4, 8])

@@ -81,11 +81,11 @@ LOCKSTEP_SPECS = [(700, 10), (1500, 30), (900, 62), (1, 5), (0, 20), (610, 94), 
                   (350, 75)]
 
 
-@pytest.mark.parametrize("ntheta", [2, 4, 8])
+@pytest.mark.parametrize("ntheta", [4, 8, 12])
 @pytest.mark.parametrize("with_grad", [True, False])
 def test_lockstep_groups_equal_one_vector_workgroups_bitwise(v, with_grad, ntheta):
-    """Several parameter vectors per workgroup (shared gather, shared diagonal factorisations) give the bits of
-    one vector per workgroup, for every class shape, with an invalid vector inside a group."""
+    """Several parameter vectors per workgroup (shared gather and pair distances) give the bits of one vector
+    per workgroup, for every class shape, with an invalid vector inside a group."""
     import torch
     rng = np.random.default_rng(81 + ntheta)
     nu = 2.5

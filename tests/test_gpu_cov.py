@@ -267,22 +267,27 @@ def test_autograd_under_a_covariance_model(v):
     np.testing.assert_allclose(th.grad.cpu().numpy(), gwant, rtol=REL_GRAD, atol=REL_GRAD * np.abs(gwant).max())
 
 
-def test_batched_plan_under_a_covariance_model(v):
-    """Fields of uneven n and m with several parameter vectors, power exponential on great-circle
-    distances, in one plan and one captured graph: every evaluation bitwise equal to its single call."""
+@pytest.mark.parametrize("cov", [(1, 1, 0.8), (1, 0, 2.0), (0, 1, 2.5)])
+def test_batched_plan_under_a_covariance_model(v, cov):
+    """Fields of uneven n and m with several parameter vectors (four-vector lockstep workgroups with shared
+    distances at m = 10 and 45, one vector per workgroup at m = 70), power exponential and Matern on great-circle or
+    Euclidean distances, in one plan and one captured graph: every evaluation bitwise equal to its single
+    call."""
     import torch
     rng = np.random.default_rng(1560)
-    cov = (1, 1, 0.8)
     dev = torch.device("cuda:0")
     fields = []
     for n, m in ((3000, 10), (5000, 45), (2000, 70)):
-        locs, z = field(rng, n, 1)
-        nbr = oracle.knn_rows(locs, m, metric=1, threads=16)
+        locs, z = field(rng, n, cov[1])
+        nbr = oracle.knn_rows(locs, m, metric=cov[1], threads=16)
         fields.append(tuple(torch.from_numpy(a).to(dev) for a in (locs, z, nbr)) + (m,))
-    thetas = torch.from_numpy(np.stack([np.column_stack([rng.uniform(0.5, 2, 4), rng.uniform(20, 80, 4),
+    scale = 1.0 if cov[1] == 1 else 1e-3  # ranges in km, or in the unit square
+    thetas = torch.from_numpy(np.stack([np.column_stack([rng.uniform(0.5, 2, 4), scale * rng.uniform(20, 80, 4),
                                                          rng.uniform(1e-3, 1e-2, 4)]) for _ in fields])).to(dev)
     thetas = thetas.contiguous()
     plan = v.BatchedPlan(fields, 4, 0.0, True, cov=cov)
+    print("classes", plan.classes(), "groups", plan.groups(), flush=True)
+    assert 4 in plan.groups()
     out, grad, st = plan(thetas)
     g_out, g_grad, g_st = plan.outputs()
     graph = plan.capture(thetas, g_out, g_grad, g_st)
