@@ -20,9 +20,11 @@ def assert_total_close(got, ref, rel, what=""):
 def assert_grad_close(got, ref, gterms_abs_sum, rel, what=""):
     """Per component: |got - ref| <= rel * max(|ref|, 1e-3 * sum_i |g_i|).
 
-    The floor covers components that cancel to near zero: summing n terms in a
-    different order moves the total by about n * eps * sum_i |g_i|, far below
-    1e-3 * rel * sum_i |g_i|."""
+    The floor covers components that cancel to near zero.  With rel = 1e-9 it
+    is an absolute bound of 1e-12 * sum_i |g_i|: the per-term gradients must
+    agree to about 1e-12 of their magnitude on average, the agreement of two
+    FP64 evaluations of well-conditioned terms; summing n terms in another
+    order moves the total by about n * eps * sum_i |g_i|, far below that."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     scale = np.maximum(np.abs(ref), 1e-3 * np.asarray(gterms_abs_sum))
