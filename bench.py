@@ -45,15 +45,20 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # HBM traffic of the conditional kernel per launch on the default workload,
 # from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch) with --copy-probe: the probe's 512 MiB device copy reads
-# 262167.8 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
-# scale factors (the counts of the second of three dispatches).  It describes
-# the kernel sources it was measured on only, so it is reported when their
-# digest still matches (kernel_sources_digest).
+# 262167.7 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
+# scale factors (the counts of the second of three dispatches).  The FP64
+# instruction counters of the same kernel (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
+# SQ_INSTS_VALU_MFMA_MOPS_F64, one run of their own) give the FP64 flops it
+# executes per launch: 64 lanes x (ADD + MUL + TRANS + 2 FMA) + 512 x MOPS.
+# The record describes the kernel sources it was measured on only, so it is
+# reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c6baf5f1ab8baac2b4ed44e9692cdde1719a4758c07d48dd86a55e9cda90bd16",
+    "sources_sha256": "c6f6f3ffcf4a7a6a8efdf50e91bd0044cc58035ebf347c6b9ec8a68a427d70da",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 9753399.75, "fetch_factor": 524288.0 / 262167.8125,
-    "write_kib_raw": 8413467.46875, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 9753267.375, "fetch_factor": 524288.0 / 262167.6875,
+    "write_kib_raw": 8414299.5, "write_factor": 524288.0 / 524288.0,
+    "f64_add": 1628957056.0, "f64_mul": 3441903358.0, "f64_fma": 8037825600.0, "f64_trans": 433989312.0,
+    "f64_mfma_mops": 1792000000.0,
 }
 
 
@@ -80,6 +85,14 @@ def measured_traffic_bytes(workload: str, variant: str):
     if t["workload"] != workload or t["variant"] != variant or t["sources_sha256"] != kernel_sources_digest():
         return None
     return (t["fetch_kib_raw"] * t["fetch_factor"] + t["write_kib_raw"] * t["write_factor"]) * 1024.0
+
+
+def measured_fp64_flops(workload: str, variant: str):
+    """FP64 flops the kernel executes per launch, from its instruction counters (None if they are stale)."""
+    t = MEASURED_TRAFFIC
+    if t["workload"] != workload or t["variant"] != variant or t["sources_sha256"] != kernel_sources_digest():
+        return None
+    return 64.0 * (t["f64_add"] + t["f64_mul"] + t["f64_trans"] + 2.0 * t["f64_fma"]) + 512.0 * t["f64_mfma_mops"]
 
 
 def la_flops_per_conditional(k: np.ndarray, with_grad: bool) -> np.ndarray:
@@ -649,6 +662,13 @@ def main():
         rec["roofline"]["traffic"] = (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
     else:
         rec["roofline"]["traffic"] = measured_traffic_bytes(w.name, names.get(variant, variant))
+    executed = measured_fp64_flops(w.name, names.get(variant, variant))
+    if executed is not None:
+        # counter-based FP64 rate beside the algorithmic one (covariance evaluation, repeated rows
+        # and padding included), over the same live launch time
+        rate = executed / (rec["roofline"]["launch_ms"] * 1e-3) / 1e12
+        rec["roofline"]["executed_fp64"] = {"flops_per_launch": executed, "tflops": rate,
+                                            "frac": rate / FP64_PEAK_TFLOPS, "source": "rocprofv3 --pmc"}
     if args.copy_probe:
         src = torch.empty(512 << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)

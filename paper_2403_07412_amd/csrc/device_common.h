@@ -226,9 +226,15 @@ __device__ __forceinline__ double pair_dist_pow(double xa, double ya, double ca,
 template <int KC, bool WITH_D>
 __device__ __forceinline__ void cov_from_dist(double da, const Params &P, double s2b, const double *tab, double &c,
                                               double &db) {
-    const double r = da * P.inv_beta;
-    const double e = exp_neg_tab(r, tab);
+    double r = da * P.inv_beta;
     constexpr int F = kc_family(KC);
+    // for nu = 3/2 and 5/2, r is opaque to the optimiser: 1 + r below could
+    // be fused with the product that forms r in one kernel and not in another
+    // (it was, for nu = 3/2 on great-circle distances), and kernels that share
+    // distances between parameter vectors must give the bits of those that do
+    // not
+    if constexpr (F == 1 || F == 2) asm volatile("" : "+v"(r));
+    const double e = exp_neg_tab(r, tab);
     if constexpr (F == 0 || F == 3) {
         c = P.sigma2 * e;
         if constexpr (WITH_D) db = s2b * (r * e);

@@ -81,14 +81,13 @@ LOCKSTEP_SPECS = [(700, 10), (1500, 30), (900, 62), (1, 5), (0, 20), (610, 94), 
                   (350, 75)]
 
 
-@pytest.mark.parametrize("ntheta", [4, 8, 12])
+@pytest.mark.parametrize("ntheta,nu", [(4, 2.5), (8, 1.5), (12, 0.5)])
 @pytest.mark.parametrize("with_grad", [True, False])
-def test_lockstep_groups_equal_one_vector_workgroups_bitwise(v, with_grad, ntheta):
+def test_lockstep_groups_equal_one_vector_workgroups_bitwise(v, with_grad, ntheta, nu):
     """Several parameter vectors per workgroup (shared gather and pair distances) give the bits of one vector
     per workgroup, for every class shape, with an invalid vector inside a group."""
     import torch
     rng = np.random.default_rng(81 + ntheta)
-    nu = 2.5
     fields = make_fields(rng, LOCKSTEP_SPECS, nu)
     th = random_thetas(rng, len(LOCKSTEP_SPECS), ntheta)
     th[2, 1] = [-1.0, 0.1, 0.0]

@@ -267,7 +267,7 @@ def test_autograd_under_a_covariance_model(v):
     np.testing.assert_allclose(th.grad.cpu().numpy(), gwant, rtol=REL_GRAD, atol=REL_GRAD * np.abs(gwant).max())
 
 
-@pytest.mark.parametrize("cov", [(1, 1, 0.8), (1, 0, 2.0), (0, 1, 2.5)])
+@pytest.mark.parametrize("cov", [(1, 1, 0.8), (1, 0, 2.0), (0, 1, 2.5), (0, 1, 1.5)])
 def test_batched_plan_under_a_covariance_model(v, cov):
     """Fields of uneven n and m with several parameter vectors (four-vector lockstep workgroups with shared
     distances at m = 10 and 45, one vector per workgroup at m = 70), power exponential and Matern on great-circle or
