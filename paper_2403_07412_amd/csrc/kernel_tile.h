@@ -112,12 +112,19 @@ static_assert(TileLds<5, 2, false, false, 2>::TOTAL == tile_lds_doubles(5, 2, fa
 __host__ __device__ constexpr int lockstep_group(int T, int W) { return (T <= 6 && W == 1) ? 4 : 1; }
 
 // Shapes measured faster with one more workgroup per CU than the register
-// estimate below allows, at the price of a small spill: T = 8, W = 4 (m from
-// 110 to 125), value + gradient 67.0 ms at four workgroups (11 VGPRs spilled)
-// against 79.3 ms at three for the 10^6-point, m = 120 field; a fifth
-// workgroup (102 VGPRs) spilled more and took 91 ms.  Other shapes keep the
-// estimate.
-__host__ __device__ constexpr bool tile_measured_raise(int T, int W, bool gcd) { return T == 8 && W == 4 && !gcd; }
+// estimate below allows, at the price of a small spill:
+//   T = 8, W = 4 (m from 110 to 125): value + gradient 67.0 ms at four
+//     workgroups (9-11 VGPRs spilled) against 79.3 ms at three for the
+//     10^6-point, m = 120 field; a fifth workgroup (102 VGPRs) spilled more
+//     and took 91 ms;
+//   T = 10, W = 4 (m from 142 to 157): 32.5 ms at three workgroups against
+//     41.7 ms at two (34.1 ms at four) for 250,000 uniform points, m = 150,
+//     nu = 3/2, value + gradient.
+// T = 7 and 9 with W = 4 measured no faster one workgroup up.  Other shapes
+// keep the estimate.
+__host__ __device__ constexpr bool tile_measured_raise(int T, int W, bool gcd) {
+    return (T == 8 || T == 10) && W == 4 && !gcd;
+}
 
 // Occupancy target (wavefronts per SIMD) the register allocation aims at.
 // Workgroups per CU are limited by LDS and by registers: each lane holds 8
