@@ -53,10 +53,10 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # The record describes the kernel sources it was measured on only, so it is
 # reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "c6f6f3ffcf4a7a6a8efdf50e91bd0044cc58035ebf347c6b9ec8a68a427d70da",
+    "sources_sha256": "d2bbced08eefa9168ea8fbfca4730818e13dbb77052942c410a9947ea6d8ad37",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 9753267.375, "fetch_factor": 524288.0 / 262167.6875,
-    "write_kib_raw": 8414299.5, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 9749240.6667, "fetch_factor": 524288.0 / 262168.3125,
+    "write_kib_raw": 8414153.3125, "write_factor": 524288.0 / 524288.0,
     "f64_add": 1628957056.0, "f64_mul": 3441903358.0, "f64_fma": 8037825600.0, "f64_trans": 433989312.0,
     "f64_mfma_mops": 1792000000.0,
 }

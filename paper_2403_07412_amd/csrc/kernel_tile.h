@@ -119,11 +119,14 @@ __host__ __device__ constexpr int lockstep_group(int T, int W) { return (T <= 6 
 //     and took 91 ms;
 //   T = 10, W = 4 (m from 142 to 157): 32.5 ms at three workgroups against
 //     41.7 ms at two (34.1 ms at four) for 250,000 uniform points, m = 150,
-//     nu = 3/2, value + gradient.
-// T = 7 and 9 with W = 4 measured no faster one workgroup up.  Other shapes
-// keep the estimate.
+//     nu = 3/2, value + gradient;
+//   T = 4, W = 2 (m from 47 to 62; LDS leaves room only without the
+//     gradient): 2.82 ms at nine workgroups against 2.89 ms at eight for the
+//     same points at m = 60, value only.
+// T = 7 and 9 with W = 4, T = 2 to 4 with W = 1 and T = 3, 5, 6 with W = 2
+// measured no faster one workgroup up.  Other shapes keep the estimate.
 __host__ __device__ constexpr bool tile_measured_raise(int T, int W, bool gcd) {
-    return (T == 8 || T == 10) && W == 4 && !gcd;
+    return ((T == 8 || T == 10) && W == 4 && !gcd) || (T == 4 && W == 2 && !gcd);
 }
 
 // Occupancy target (wavefronts per SIMD) the register allocation aims at.
