@@ -151,20 +151,35 @@ int run_batched(const vecchia_plan *p, const double *thetas, double *out, double
     for (int c = 0; c < nc; ++c) {
         const ClassPlan &C = p->classes[c];
         EvalArgs a{};
-        a.k.theta = thetas;
-        a.k.fields = dfields;
-        a.k.fidx = (const int32_t *)(w + C.off_fidx);
-        a.k.item0 = (const int64_t *)(w + C.off_item0);
-        a.k.nfc = (int32_t)C.fidx.size();
-        a.k.ntheta = p->ntheta;
         a.k.ell = vals;
         a.k.ell_stride = 4;
         a.k.g = vals + 1;
         a.k.g_stride = 4;
         a.k.flags = flags;
         a.k.alpha = p->alpha;
-        a.t_begin = 0;
-        a.t_end = C.item0.back();
+        if (C.fidx.size() == 1 && p->ntheta == 1 && C.group == 1) {
+            // one field and one vector: nothing to batch, the single-field
+            // launch (rows offset by the field's)
+            const FieldDev &F = p->fields[C.fidx[0]];
+            a.k.locs = F.locs;
+            a.k.z = F.z;
+            a.k.nbr = F.nbr;
+            a.k.n = F.n;
+            a.k.m = (int32_t)F.m;
+            a.k.theta = thetas + 3 * F.eval0;
+            a.k.row0 = -F.vals0;
+            a.t_begin = 0;
+            a.t_end = F.n;
+        } else {
+            a.k.theta = thetas;
+            a.k.fields = dfields;
+            a.k.fidx = (const int32_t *)(w + C.off_fidx);
+            a.k.item0 = (const int64_t *)(w + C.off_item0);
+            a.k.nfc = (int32_t)C.fidx.size();
+            a.k.ntheta = p->ntheta;
+            a.t_begin = 0;
+            a.t_end = C.item0.back();
+        }
         a.m_max = C.m_max;
         a.group = C.group;
         const int rc = launch_any(p->nuc, p->grad, C.variant, a, s);

@@ -103,6 +103,16 @@ struct KernelArgs {
     double *pmean, *pvar;
 };
 
+// r / ntheta for an item offset r >= 0 of the lockstep form: in 32 bits when
+// r fits (a 64-bit division is a long instruction sequence at the start of
+// every workgroup).  The one-vector form keeps the plain division: the
+// branch costs the m = 120 kernel a scalar spill.
+__device__ __forceinline__ int64_t item_point(int64_t r, int32_t ntheta) {
+    if (ntheta == 1) return r;
+    if ((r >> 32) == 0) return (int64_t)((uint32_t)r / (uint32_t)ntheta);
+    return r / ntheta;
+}
+
 // Evaluates item t (see KernelArgs) with one workgroup.  Failure is reported
 // through flags[row] (when given) or as atomicMin(status, t + 1) (when
 // given); failed rows hold NaN.
@@ -196,7 +206,7 @@ __device__ __forceinline__ void cond_item_group(const KernelArgs &a, int64_t t0,
     }
     const FieldDev &F = a.fields[a.fidx[lo]];
     const int64_t r = t - a.item0[lo];
-    const int64_t ip = r / a.ntheta;
+    const int64_t ip = item_point(r, a.ntheta);
     const int64_t q = r - ip * a.ntheta;
     const int64_t n = F.n, i = n - 1 - ip;
     const int64_t row = F.vals0 + q * n + i;
