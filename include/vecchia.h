@@ -272,6 +272,12 @@ typedef struct vecchia_graph vecchia_graph;
  * / vecchia_autotune) holds for the largest m of the class.  The plan is a host
  * object: planning allocates no device memory, creates no stream and does not
  * synchronise.  The field arrays must stay valid while the plan is used.
+ * A class of up to five tile rows (m <= 78) whose ntheta is a multiple of 4
+ * takes the one-wavefront variant instead, in lockstep groups
+ * (vecchia_plan_class_group), unless the table holds the unblocked variant
+ * or lockstep forms are off (vecchia_set_lockstep).  vecchia_plan_class_info
+ * reports the variant a class uses; every result is bitwise equal to the
+ * single call with that variant.
  * Returns VECCHIA_OK, VECCHIA_EINVAL, VECCHIA_EUNSUPPORTED (m, nf or
  * nf * ntheta too large).
  */
@@ -294,10 +300,11 @@ int vecchia_plan_class_info(const vecchia_plan *plan, int32_t c, int32_t *tile_r
                             int32_t *nfields, int64_t *items);
 
 /* Parameter vectors one workgroup of class c evaluates together: 4 when the
- * class's variant has one wavefront per conditional (up to 94 neighbours) and
- * ntheta is a multiple of 4, else 1.  The four vectors of a point share the
- * gathered neighbours and the pair distances; each vector's result is bitwise
- * the single-vector one.  -VECCHIA_EINVAL for a bad plan or class. */
+ * class has at most five tile rows (m <= 78), a tiled variant and ntheta a
+ * multiple of 4 (see vecchia_plan_create), else 1.  The four vectors of a
+ * point share the gathered neighbours and the pair distances; each vector's
+ * result is bitwise the single-vector one of the same variant.
+ * -VECCHIA_EINVAL for a bad plan or class. */
 int vecchia_plan_class_group(const vecchia_plan *plan, int32_t c);
 
 /* Whether plans created from now on may use lockstep forms (default 1);
@@ -517,7 +524,10 @@ size_t vecchia_mle_workspace_size(int64_t n, int32_t m);
  * a quasi-Newton step alone, and once it backs off (or without curvature
  * information) the next trial_steps halvings of the step at once, taking
  * the longest that satisfies the Armijo condition, the step one-at-a-time
- * backtracking would take.  Synchronises the stream once per round trip.  Returns VECCHIA_OK,
+ * backtracking would take.  Round trips of four or eight vectors take the
+ * plan's lockstep form, so at 63..78 neighbours their values and those of
+ * single-vector round trips come from different kernel variants and may
+ * differ in the last bits.  Synchronises the stream once per round trip.  Returns VECCHIA_OK,
  * VECCHIA_EINVAL (bad arguments or options, or theta0 does not evaluate),
  * VECCHIA_EUNSUPPORTED, VECCHIA_EWORKSPACE or VECCHIA_EHIP.
  */

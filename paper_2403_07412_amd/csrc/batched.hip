@@ -264,11 +264,20 @@ int plan_build(const vecchia_field *fields, int32_t nf, int32_t ntheta, const ve
             C.m_max = std::max(C.m_max, fields[f].m);
         }
         C.variant = resolve_variant(C.m_max, p->grad, 0);
-        // several parameter vectors of a point share one workgroup when the
-        // shape has a lockstep form and the vectors divide into its groups
-        const int W = variant_waves(C.variant);
-        const int G = W > 0 ? lockstep_group(T, W) : 1;
-        if (g_lockstep.load() && G > 1 && ntheta % G == 0) C.group = G;
+        // Several parameter vectors of a point share one workgroup (lockstep)
+        // when they divide into groups of four and the class fits the
+        // one-wavefront form (up to five tile rows).  That form replaces any
+        // tiled variant the table holds for single calls: on 64 vectors at
+        // 10^5 points it took 36.1 against 44.7 ms (m = 40), 60.7 against
+        // 71.8 ms (m = 60) and 105.2 against 115.7 ms (m = 75) without the
+        // gradient, 158.5 against 183.0 ms (m = 75) with it, each against
+        // one vector per workgroup of the table's two-wavefront variant.
+        const int G1 = lockstep_group(T, 1);
+        if (g_lockstep.load() && variant_waves(C.variant) > 0 && G1 > 1 && ntheta % G1 == 0 &&
+            variant_feasible(V_TILE_W1, C.m_max)) {
+            C.variant = V_TILE_W1;
+            C.group = G1;
+        }
         p->classes.push_back(C);
     }
     // device table: the field array, then per class its field list and item offsets

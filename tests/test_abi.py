@@ -115,12 +115,10 @@ def test_batched_workspace_query_and_plan_are_host_only(lib):
         assert lib.vecchia_plan_destroy(handle) == 0
 
 
-def _expected_group(T, variant, ntheta):
-    """Lockstep group size of a class: four vectors, one wavefront each, for one-wavefront variants up to six
-    tile rows."""
-    waves = {2: 1, 3: 2, 4: 4, 5: 8}.get(variant, 0)
-    G = 4 if T <= 6 and waves == 1 else 1
-    return G if ntheta % G == 0 else 1
+def _expected_group(T, ntheta):
+    """Lockstep group size of a class: four vectors, one wavefront each, up to five tile rows (the one-wavefront
+    variant holds at most 20 tiles) when the vectors divide into fours."""
+    return 4 if T <= 5 and ntheta % 4 == 0 else 1
 
 
 @pytest.mark.parametrize("ntheta", [1, 2, 3, 4, 8])
@@ -128,6 +126,7 @@ def _expected_group(T, variant, ntheta):
 def test_plan_picks_lockstep_groups_on_the_host(lib, ntheta, with_grad):
     import paper_2403_07412_amd as v
     specs = [(1000, 10), (1000, 30), (1000, 45), (1000, 60), (1000, 75), (1000, 94), (1000, 95), (1000, 120)]
+    m_of = {(m + 2 + 15) // 16: m for _, m in specs}  # one field per tile class
     arr = _fake_fields(v, specs)
     T, var = ctypes.c_int32(), ctypes.c_int32()
     for enable in (1, 0):
@@ -143,7 +142,10 @@ def test_plan_picks_lockstep_groups_on_the_host(lib, ntheta, with_grad):
             for c in range(lib.vecchia_plan_num_classes(handle)):
                 assert lib.vecchia_plan_class_info(handle, c, ctypes.byref(T), ctypes.byref(var), None, None) == 0
                 g = lib.vecchia_plan_class_group(handle, c)
-                assert g == (_expected_group(T.value, var.value, ntheta) if enable else 1), (T.value, var.value)
+                assert g == (_expected_group(T.value, ntheta) if enable else 1), (T.value, var.value)
+                # lockstep classes run the one-wavefront variant, the others the table's
+                table = lib.vecchia_get_variant(m_of[T.value], with_grad)
+                assert var.value == (2 if g == 4 else table), (T.value, var.value, table)
                 groups.append(g)
             if enable and ntheta % 4 == 0:
                 assert max(groups) == 4

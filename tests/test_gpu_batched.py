@@ -77,6 +77,24 @@ def test_batched_equals_single_calls_bitwise_and_oracle(v, with_grad):
     plan.close()
 
 
+def table_as_plan(v, ms, plan, with_grad):
+    """Points the variant table at the variant each m's tile class uses in `plan` (lockstep classes take the
+    one-wavefront variant); returns the previous entries for restore_table."""
+    var_of = {T: var for T, var, _, _ in plan.classes()}
+    old = {}
+    for m in ms:
+        T = (m + 2 + 15) // 16
+        if m not in old and T in var_of:
+            old[m] = v.vecchia_get_variant(m, with_grad)
+            v.vecchia_set_variant(m, with_grad, var_of[T])
+    return old
+
+
+def restore_table(v, old, with_grad):
+    for m, var in old.items():
+        v.vecchia_set_variant(m, with_grad, var)
+
+
 LOCKSTEP_SPECS = [(700, 10), (1500, 30), (900, 62), (1, 5), (0, 20), (610, 94), (400, 120), (64, 3), (17, 40),
                   (350, 75)]
 
@@ -93,15 +111,20 @@ def test_lockstep_groups_equal_one_vector_workgroups_bitwise(v, with_grad, nthet
     th[2, 1] = [-1.0, 0.1, 0.0]
     thetas = torch.from_numpy(th).cuda()
     prev = v.set_lockstep(True)
+    old = {}
     try:
         plan = v.BatchedPlan([f[1] for f in fields], ntheta, nu, with_grad)
         v.set_lockstep(False)
+        # one vector per workgroup with the variants the lockstep plan uses
+        old = table_as_plan(v, [m for _, m in LOCKSTEP_SPECS], plan, with_grad)
         plan1 = v.BatchedPlan([f[1] for f in fields], ntheta, nu, with_grad)
     finally:
         v.set_lockstep(prev)
+        restore_table(v, old, with_grad)
     groups = plan.groups()
     print("classes", plan.classes(), "groups", groups, flush=True)
     assert max(groups) > 1 and all(g == 1 for g in plan1.groups())
+    assert [c[1] for c in plan.classes()] == [c[1] for c in plan1.classes()]
     out, grad, status = plan(thetas)
     out1, grad1, status1 = plan1(thetas)
     torch.cuda.synchronize()

@@ -295,10 +295,17 @@ def test_batched_plan_under_a_covariance_model(v, cov):
     torch.cuda.synchronize()
     assert (st.cpu().numpy() == 0).all() and (g_st.cpu().numpy() == 0).all()
     assert torch.equal(out, g_out) and torch.equal(grad, g_grad)
+    # single calls with the variant of each field's class (lockstep classes run the one-wavefront one)
+    var_of = {T: var for T, var, _, _ in plan.classes()}
     for q, (L, Z, N, m) in enumerate(fields):
-        for p in range(4):
-            o, g, s = v.vecchia_loglik_cov(L, Z, N, m, cov, thetas[q, p].contiguous(), with_grad=True)
-            torch.cuda.synchronize()
-            assert o.item() == out[q, p].item() and torch.equal(g, grad[q, p])
+        prev = v.vecchia_get_variant(m, True)
+        v.vecchia_set_variant(m, True, var_of[(m + 2 + 15) // 16])
+        try:
+            for p in range(4):
+                o, g, s = v.vecchia_loglik_cov(L, Z, N, m, cov, thetas[q, p].contiguous(), with_grad=True)
+                torch.cuda.synchronize()
+                assert o.item() == out[q, p].item() and torch.equal(g, grad[q, p])
+        finally:
+            v.vecchia_set_variant(m, True, prev)
     graph.close()
     plan.close()
