@@ -106,10 +106,12 @@ static_assert(TileLds<4, 1, true, true, 4>::TOTAL == tile_lds_doubles(4, 1, true
 static_assert(TileLds<5, 2, false, false, 2>::TOTAL == tile_lds_doubles(5, 2, false, false, 2), "LDS estimate out of date");
 
 // Parameter vectors a workgroup evaluates in lockstep, per shape: four for
-// the one-wavefront shapes up to six tile rows, where the four wavefronts
-// share the gathered neighbours and the pair distances; other shapes keep one
-// vector (G = 1).  Only these group sizes are compiled.
-__host__ __device__ constexpr int lockstep_group(int T, int W) { return (T <= 6 && W == 1) ? 4 : 1; }
+// the one-wavefront shapes (up to five tile rows: six rows make 21 tiles,
+// past the 20 one wavefront holds), where the four wavefronts share the
+// gathered neighbours and the pair distances; other shapes keep one vector
+// (G = 1).
+// Only these group sizes are compiled.
+__host__ __device__ constexpr int lockstep_group(int T, int W) { return (T <= 5 && W == 1) ? 4 : 1; }
 
 // Shapes measured faster with one more workgroup per CU than the register
 // estimate below allows, at the price of a small spill:
