@@ -69,14 +69,14 @@ __host__ __device__ constexpr int tiles_per_wave(int T, int W) { return (tile_co
 // lockstep keeps G copies of everything that depends on the parameters (CUR,
 // SLOT, YP, Q, UB, SCAL, RED); the gathered coordinates, observations and the
 // exponential table are shared.  G = 1 is the one-vector layout.  With one
-// wavefront per vector (INPLACE) there is no CUR: each vector's wavefront
-// stores diagonal tile t + 1 into slot t + 1 once its trailing updates have
-// read X_(t+1) there, and the tile is factored in place.
+// wavefront per vector (INPLACE, also for G = 1) there is no CUR: the
+// wavefront stores diagonal tile t + 1 into slot t + 1 once its trailing
+// updates have read X_(t+1) there, and the tile is factored in place.
 template <int T, int W, bool GRAD, bool GCD = false, int G = 1>
 struct TileLds {
     static constexpr int KP = 16 * T;
     static constexpr int DS = 288;                        // a 16 x 17 tile, then 16 inverse pivots
-    static constexpr bool INPLACE = G > 1 && W == 1;
+    static constexpr bool INPLACE = W == 1;
     static constexpr int NPAR = (W > 1 && T > 1) ? 2 : 1;
     static constexpr int CUR = 0;                         // [G][NPAR][DS]  diagonal tile / its factor
     static constexpr int SLOT = CUR + (INPLACE ? 0 : G * NPAR * DS);  // [G][T][DS] panel tiles / factors
@@ -86,19 +86,19 @@ struct TileLds {
     static constexpr int Q = YP + G * KP;                 // [G][KP][2]     back-substitution right-hand sides (gradient)
     static constexpr int UB = Q + (GRAD ? G * 2 * KP : 0);    // [G][KP][2] solutions (u, b) (gradient)
     static constexpr int SCAL = UB + (GRAD ? G * 2 * KP : 0); // [G][16]    scalars: [0] L_kk
-    static constexpr int RED = SCAL + G * 16;             // [G][2][32]     reductions (two values, up to 8 waves x 4 rows)
-    static constexpr int EXPT = RED + G * 64;             // [64][2]        2^(j/64) as hi, lo for exp_neg_tab
+    static constexpr int RED = SCAL + G * 16;             // [G][2][4W]     reductions (two values, W waves x 4 rows)
+    static constexpr int EXPT = RED + G * 8 * W;          // [64][2]        2^(j/64) as hi, lo for exp_neg_tab
     static constexpr int CL = EXPT + 2 * kExpTableSize;   // [KP]           cos(latitude) (great-circle codes only)
     static constexpr int TOTAL = CL + (GCD ? KP : 0);
     static constexpr size_t BYTES = (size_t)TOTAL * sizeof(double);
     // per-parameter-vector strides
-    static constexpr int CUR_G = NPAR * DS, SLOT_G = T * DS, YP_G = KP, QUB_G = 2 * KP, SCAL_G = 16, RED_G = 64;
+    static constexpr int CUR_G = NPAR * DS, SLOT_G = T * DS, YP_G = KP, QUB_G = 2 * KP, SCAL_G = 16, RED_G = 8 * W;
 };
 
 // TileLds<T, W, grad, gcd, G>::TOTAL, for the occupancy estimate.
 __host__ __device__ constexpr int tile_lds_doubles(int T, int W, bool grad, bool gcd, int G = 1) {
-    return (G > 1 && W == 1 ? 0 : G * ((W > 1 && T > 1) ? 2 : 1) * 288) + G * T * 288 +
-           16 * T * (3 + G * (1 + (grad ? 4 : 0)) + (gcd ? 1 : 0)) + G * (16 + 64) + 2 * kExpTableSize;
+    return (W == 1 ? 0 : G * ((W > 1 && T > 1) ? 2 : 1) * 288) + G * T * 288 +
+           16 * T * (3 + G * (1 + (grad ? 4 : 0)) + (gcd ? 1 : 0)) + G * (16 + 8 * W) + 2 * kExpTableSize;
 }
 static_assert(TileLds<8, 4, true, false>::TOTAL == tile_lds_doubles(8, 4, true, false), "LDS estimate out of date");
 static_assert(TileLds<3, 1, false, true>::TOTAL == tile_lds_doubles(3, 1, false, true), "LDS estimate out of date");
@@ -161,14 +161,16 @@ __host__ __device__ constexpr int tile_waves_per_simd(int T, int W, bool keep_d,
 // exponential) a logarithm and an exponential per entry: there the tiles are
 // kept whenever two wavefronts per SIMD still fit (measured: the 250,000-point
 // great-circle power-exponential gradient took 11.7 ms keeping them at two
-// wavefronts per SIMD, 17.0 ms recomputing at three).  Lockstep workgroups
-// follow the one-vector decision: the two ways round the derivative
-// contract their arithmetic differently, and the lockstep results must be
-// the one-vector bits.
+// wavefronts per SIMD, 17.0 ms recomputing at three).  The one-wavefront
+// shape of two tile rows keeps them as well (measured: 250,000 points,
+// m = 30, value + gradient 1.25 ms keeping at four wavefronts per SIMD, 1.33
+// ms recomputing at five).  Lockstep workgroups follow the one-vector
+// decision: the two ways round the derivative contract their arithmetic
+// differently, and the lockstep results must be the one-vector bits.
 __host__ __device__ constexpr bool keep_dbeta(int T, int W, bool gcd = false) {
     return VECCHIA_KEEP_DBETA &&
            (tile_waves_per_simd(T, W, true, true, gcd) >= tile_waves_per_simd(T, W, false, true, gcd) ||
-            (gcd && tile_waves_per_simd(T, W, true, true, gcd) >= 2));
+            (gcd && tile_waves_per_simd(T, W, true, true, gcd) >= 2) || (T == 2 && W == 1));
 }
 
 // Tile enumeration: column C descending, row R ascending inside a column, so
@@ -493,11 +495,11 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     double *const YPq = smem + Ls::YP + wq * Ls::YP_G;
     double *const SCALq = smem + Ls::SCAL + wq * Ls::SCAL_G;
     // synchronisation of the wavefronts that share a vector's tiles: the whole
-    // workgroup, except in lockstep groups of one wavefront per vector, where
-    // each wavefront works on its own vector alone between the shared phases
-    // (the gather, and the distance exchanges)
+    // workgroup, except with one wavefront per vector, where each wavefront
+    // works on its own vector alone (in lockstep groups, between the shared
+    // phases: the gather, and the distance exchanges)
     auto group_sync = [&]() {
-        if constexpr (G > 1 && W == 1)
+        if constexpr (W == 1)
             wave_lds_sync();
         else
             __syncthreads();
@@ -575,7 +577,7 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
     // register) pair, 64 lanes at a time, into the panel slots past slot 0,
     // which hold nothing yet (and nothing any more when the gradient's
     // contraction needs the distances again).
-    constexpr bool SHARE_D = Ls::INPLACE && T >= 2;
+    constexpr bool SHARE_D = Ls::INPLACE && G > 1 && T >= 2;
     constexpr int DCH = SHARE_D ? ((T - 1) * DS) / kWave : 1;  // 64-double chunks per vector past slot 0
     static_assert(!SHARE_D || G * DCH >= 4 * NTW, "the shared distances fit in the panel slots");
     auto dslot = [&](int p) -> double * { return smem + Ls::SLOT + (p / DCH) * Ls::SLOT_G + DS + (p % DCH) * kWave; };

@@ -321,7 +321,13 @@ inline bool variant_feasible(int variant, int m) {
 // 300,000 points, nu = 1/2, once the occupancy targets allowed a fifth
 // wavefront per SIMD).  Three and four tile rows favour one wavefront with
 // the gradient and two without; up to six rows two wavefronts; beyond, four
-// (eight wavefronts lose to their barriers at every size).
+// (eight wavefronts lose to their barriers at every size).  Since the
+// one-wavefront kernels factor their diagonal tiles in place, one wavefront
+// is also the faster value-only kernel at three and four rows for the Matern
+// codes on Euclidean distances (250,000 points: 1.56 against 1.77 ms at
+// m = 40, 2.78 against 2.83 ms at m = 60), but not for kriging with the
+// great-circle power exponential (25,000 predictions at m = 60: 0.84 against
+// 0.69 ms); the table has no covariance code, so two wavefronts stay.
 inline int default_variant(int m, bool grad) {
     const int T = tile_rows(m);
     if (T <= 2) return V_TILE_W1;
