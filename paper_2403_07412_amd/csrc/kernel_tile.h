@@ -83,9 +83,9 @@ struct TileLds {
     static constexpr int XY = SLOT + G * T * DS;          // [KP][2]        coordinates
     static constexpr int ZV = XY + 2 * KP;                // [KP]           observations
     static constexpr int YP = ZV + KP;                    // [G][KP]        factor row k+1
-    static constexpr int Q = YP + G * KP;                 // [G][KP][2]     back-substitution right-hand sides (gradient)
-    static constexpr int UB = Q + (GRAD ? G * 2 * KP : 0);    // [G][KP][2] solutions (u, b) (gradient)
-    static constexpr int SCAL = UB + (GRAD ? G * 2 * KP : 0); // [G][16]    scalars: [0] L_kk
+    static constexpr int Q = YP + G * KP;                 // [G][KP][2]     back-substitution right-hand sides (gradient),
+    static constexpr int UB = Q;                          //                overwritten in place by the solutions (u, b)
+    static constexpr int SCAL = Q + (GRAD ? G * 2 * KP : 0);  // [G][16]    scalars: [0] L_kk
     static constexpr int RED = SCAL + G * 16;             // [G][2][4W]     reductions (two values, W waves x 4 rows)
     static constexpr int EXPT = RED + G * 8 * W;          // [64][2]        2^(j/64) as hi, lo for exp_neg_tab
     static constexpr int CL = EXPT + 2 * kExpTableSize;   // [KP]           cos(latitude) (great-circle codes only)
@@ -98,7 +98,7 @@ struct TileLds {
 // TileLds<T, W, grad, gcd, G>::TOTAL, for the occupancy estimate.
 __host__ __device__ constexpr int tile_lds_doubles(int T, int W, bool grad, bool gcd, int G = 1) {
     return (W == 1 ? 0 : G * ((W > 1 && T > 1) ? 2 : 1) * 288) + G * T * 288 +
-           16 * T * (3 + G * (1 + (grad ? 4 : 0)) + (gcd ? 1 : 0)) + G * (16 + 8 * W) + 2 * kExpTableSize;
+           16 * T * (3 + G * (1 + (grad ? 2 : 0)) + (gcd ? 1 : 0)) + G * (16 + 8 * W) + 2 * kExpTableSize;
 }
 static_assert(TileLds<8, 4, true, false>::TOTAL == tile_lds_doubles(8, 4, true, false), "LDS estimate out of date");
 static_assert(TileLds<3, 1, false, true>::TOTAL == tile_lds_doubles(3, 1, false, true), "LDS estimate out of date");
@@ -715,13 +715,16 @@ __device__ __forceinline__ CondOut tile_conditional(const double *__restrict__ l
         const double rr = wv / Lkk;
         const double half = 0.5 * (rr * rr - 1.0 / c);
         // back substitution with L^T for both right-hand sides at once.  Q
-        // holds (q_u, q_b) pairs, UB receives (u, b).  Per tile row t, from
-        // the last: the owner of the diagonal tile solves L_tt^T x_t = q_t by
-        // substitution (lanes of row groups 0 and 1 hold the two right-hand
-        // sides, lane n entry n), then the owners of the tiles (t, C), C < t,
-        // subtract L_tC^T x_t from q_C on the matrix cores: an N-layout tile
-        // as the first operand enters as its transpose, and x_t as the second
-        // operand sits in lanes (g, j < 2), register q holding x_j[4q + g].
+        // holds (q_u, q_b) pairs, and (u, b) replace them in place (UB is
+        // the same array): block t of q is read only by the solve that
+        // writes block t of the solution, and later updates touch blocks
+        // C < t only.  Per tile row t, from the last: the owner of the
+        // diagonal tile solves L_tt^T x_t = q_t by substitution (lanes of row
+        // groups 0 and 1 hold the two right-hand sides, lane n entry n), then
+        // the owners of the tiles (t, C), C < t, subtract L_tC^T x_t from q_C
+        // on the matrix cores: an N-layout tile as the first operand enters
+        // as its transpose, and x_t as the second operand sits in lanes
+        // (g, j < 2), register q holding x_j[4q + g].
         double *Q = smem + Ls::Q + wq * Ls::QUB_G, *UB = smem + Ls::UB + wq * Ls::QUB_G;
         const double *YP = YPq;
         for (int t = tg; t < KP; t += NTG) {
