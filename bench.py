@@ -45,7 +45,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # HBM traffic of the conditional kernel per launch on the default workload,
 # from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE,
 # KiB per dispatch) with --copy-probe: the probe's 512 MiB device copy reads
-# 262167.4 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
+# 262167.3 KiB of FETCH_SIZE and 524288 KiB of WRITE_SIZE, which fixes the
 # scale factors (the kernel's counts are the mean of three dispatches).  The FP64
 # instruction counters of the same kernel (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64,
 # SQ_INSTS_VALU_MFMA_MOPS_F64, one run of their own) give the FP64 flops it
@@ -53,10 +53,10 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak: 256 CU x 2.4 G
 # The record describes the kernel sources it was measured on only, so it is
 # reported when their digest still matches (kernel_sources_digest).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "4e8987c52b37aac87fdd325c77e1e9cbea0d7462c8ce426b63f49d221043d90b",
+    "sources_sha256": "889c220c3831158fe298add76f30a8e6c52522e07d8e3b70db4fb2defa6e8b6d",
     "workload": "n1M_m120_nu0.5", "variant": "tile_w4",
-    "fetch_kib_raw": 9754663.3125, "fetch_factor": 524288.0 / 262167.4375,
-    "write_kib_raw": 8414737.2604, "write_factor": 524288.0 / 524288.0,
+    "fetch_kib_raw": 9754650.7083, "fetch_factor": 524288.0 / 262167.25,
+    "write_kib_raw": 8415836.7500, "write_factor": 524288.0 / 524288.0,
     "f64_add": 1628957056.0, "f64_mul": 3441903358.0, "f64_fma": 8037825600.0, "f64_trans": 433989312.0,
     "f64_mfma_mops": 1792000000.0,
 }

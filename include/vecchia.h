@@ -206,8 +206,11 @@ int vecchia_predict(const double *locs, const double *z, int64_t n, const double
  *                              or 8 wavefronts, Cholesky blocked by tile columns
  *                              with FP64 matrix-core trailing updates.
  * VECCHIA_VARIANT_AUTO uses the per-(m, gradient) table below, or a built-in
- * default.  A tile variant is feasible when each wavefront holds at most 20
- * tiles; vecchia_variant_feasible reports it.
+ * default: one wavefront up to 62 neighbours with the gradient (and without
+ * it for the Matern codes on Euclidean distances; two for the other codes
+ * and for kriging from 31 to 62), two up to 94, four beyond.  A tile variant
+ * is feasible when each wavefront holds at most 20 tiles;
+ * vecchia_variant_feasible reports it.
  */
 enum vecchia_variant {
     VECCHIA_VARIANT_AUTO = 0,
@@ -230,7 +233,8 @@ int vecchia_variant_feasible(int32_t m, int32_t variant);
  */
 int vecchia_set_variant(int32_t m, int32_t with_grad, int32_t variant);
 
-/* The variant the entry points use for (m, with_grad); negative on bad m. */
+/* The variant the entry points use for (m, with_grad) under the Matern codes
+ * on Euclidean distances; negative on bad m. */
 int vecchia_get_variant(int32_t m, int32_t with_grad);
 
 /*

@@ -263,7 +263,7 @@ int plan_build(const vecchia_field *fields, int32_t nf, int32_t ntheta, const ve
             C.item0.push_back(C.item0.back() + (int64_t)ntheta * fields[f].n);
             C.m_max = std::max(C.m_max, fields[f].m);
         }
-        C.variant = resolve_variant(C.m_max, p->grad, 0);
+        C.variant = resolve_variant(C.m_max, p->grad, 0, p->nuc);
         // Several parameter vectors of a point share one workgroup (lockstep)
         // when they divide into groups of four and the class fits the
         // one-wavefront form (up to five tile rows).  That form replaces any

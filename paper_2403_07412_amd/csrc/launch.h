@@ -324,14 +324,14 @@ inline bool variant_feasible(int variant, int m) {
 // (eight wavefronts lose to their barriers at every size).  Since the
 // one-wavefront kernels factor their diagonal tiles in place, one wavefront
 // is also the faster value-only kernel at three and four rows for the Matern
-// codes on Euclidean distances (250,000 points: 1.56 against 1.77 ms at
-// m = 40, 2.78 against 2.83 ms at m = 60), but not for kriging with the
+// codes on Euclidean distances (kc 0..2; 250,000 points: 1.56 against 1.77 ms
+// at m = 40, 2.78 against 2.83 ms at m = 60), but not for kriging with the
 // great-circle power exponential (25,000 predictions at m = 60: 0.84 against
-// 0.69 ms); the table has no covariance code, so two wavefronts stay.
-inline int default_variant(int m, bool grad) {
+// 0.69 ms): the other codes, kriging (kc < 0) and unknown callers keep two.
+inline int default_variant(int m, bool grad, int kc = -1) {
     const int T = tile_rows(m);
     if (T <= 2) return V_TILE_W1;
-    if (T <= 4) return grad ? V_TILE_W1 : V_TILE_W2;
+    if (T <= 4) return (grad || (kc >= 0 && kc <= 2)) ? V_TILE_W1 : V_TILE_W2;
     if (T <= 6) return V_TILE_W2;
     return V_TILE_W4;
 }
@@ -397,7 +397,7 @@ int launch_variant(int variant, const EvalArgs &a, hipStream_t s) {
 // variant table, and the launcher for any covariance code (0..7).
 int nu_code(double nu);
 int cov_code(const vecchia_cov *cov, double *alpha);
-int resolve_variant(int m, bool grad, int requested);
+int resolve_variant(int m, bool grad, int requested, int kc = -1);
 extern int g_variant[2][VECCHIA_MAX_M + 1];
 int launch_any(int kc, bool grad, int variant, const EvalArgs &a, hipStream_t s);
 

@@ -29,9 +29,9 @@ namespace vecchia {
 // host-side variant table, indexed by [with_grad][m]; 0 = default
 int g_variant[2][VECCHIA_MAX_M + 1] = {};
 
-int resolve_variant(int m, bool grad, int requested) {
+int resolve_variant(int m, bool grad, int requested, int kc) {
     int v = requested != V_AUTO ? requested : g_variant[grad ? 1 : 0][m];
-    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m, grad);
+    if (v == V_AUTO || !variant_feasible(v, m)) v = default_variant(m, grad, kc);
     return v;
 }
 
@@ -176,7 +176,7 @@ int run_sum(const double *locs, const double *z, const int32_t *nbr, int64_t n, 
     a.t_begin = 0;
     a.t_end = n;
     a.m_max = m;
-    rc = launch_any(kc, with_grad, resolve_variant(m, with_grad, variant), a, s);
+    rc = launch_any(kc, with_grad, resolve_variant(m, with_grad, variant, kc), a, s);
     if (rc != VECCHIA_OK) return rc;
     const int64_t nb = num_reduce_blocks(n);
     if (nb > 0)
@@ -214,7 +214,7 @@ int run_terms(const double *locs, const double *z, const int32_t *nbr, int64_t n
     a.t_end = nidx;
     a.m_max = m;
     hipLaunchKernelGGL(status_init_kernel, dim3(1), dim3(64), 0, s, st);
-    rc = launch_any(kc, g, resolve_variant(m, g, variant), a, s);
+    rc = launch_any(kc, g, resolve_variant(m, g, variant, kc), a, s);
     if (rc != VECCHIA_OK) return rc;
     hipLaunchKernelGGL(status_fix_kernel, dim3(1), dim3(64), 0, s, st, theta);
     return hipGetLastError() == hipSuccess ? VECCHIA_OK : VECCHIA_EHIP;
@@ -331,7 +331,7 @@ int vecchia_set_variant(int32_t m, int32_t with_grad, int32_t variant) {
 
 int vecchia_get_variant(int32_t m, int32_t with_grad) {
     if (m < 0 || m > VECCHIA_MAX_M) return -VECCHIA_EINVAL;
-    return resolve_variant(m, with_grad != 0, V_AUTO);
+    return resolve_variant(m, with_grad != 0, V_AUTO, 0);
 }
 
 int vecchia_variant_feasible(int32_t m, int32_t variant) {
